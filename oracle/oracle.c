@@ -1,0 +1,214 @@
+/* FP64 CPU oracle for finite-element element matrices.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant with the GPU library: it never forms the paper's
+ * reference tensor K or geometric tensor G (Sec. 3, eqs. 1, 6-8) and instead
+ * integrates each element directly on the physical simplex:
+ *
+ *   1. vertex coordinates in double;
+ *   2. barycentric functions from the inverse of the Vandermonde matrix with
+ *      rows [1, x_a] (LU with partial pivoting); volume = |det V| / d!;
+ *   3. a Grundmann-Moeller simplex rule (Grundmann & Moeller, SIAM J. Numer.
+ *      Anal. 15 (1978)) -- degree 3 by default, exact for P1 and P2 stiffness;
+ *   4. basis gradients at the points (P1, or P2 vertex/edge functions);
+ *   5. Laplacian: sum_k w_k grad phi_i . grad phi_j  (Sec. 3, eqs. 3-4);
+ *      elasticity: sum_k w_k Bv^T D Bv with the Voigt strain-displacement
+ *      matrix Bv and isotropic Hooke matrix D (the Lame form of Sec. 3,
+ *      eqs. 9-12; mu = 1/2, lambda = 0 gives the form of eq. 24).
+ *
+ * Gradients of L = sum_IJ dA_IJ A_IJ with respect to vertex coordinates and
+ * the Lame coefficients use the complex-step derivative (Squire & Trapp, SIAM
+ * Rev. 40 (1998)) of the same routine instantiated on double _Complex:
+ * dL/dp = Im L(p + i h) / h, exact to rounding for h = 1e-30.
+ *
+ * Conventions: reference DOF order is node-major, I = dim*a + c; P2 edges
+ * are ordered (0,1),(0,2),...,(d-1,d) after the d+1 vertices.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_LAPLACE 0
+#define ORACLE_ELASTIC 1
+
+#define ORACLE_MAX_QP 128
+
+int oracle_version(void) { return 1; }
+
+static long factorial(int k)
+{
+    long f = 1;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+/* Enumerate all beta in N^{m} with |beta| = total, calling back with each. */
+static int compositions(int total, int m, int *beta, int pos, int (*out)[4], int count)
+{
+    if (pos == m - 1) {
+        beta[pos] = total;
+        for (int j = 0; j < m; ++j) out[count][j] = beta[j];
+        return count + 1;
+    }
+    for (int b = 0; b <= total; ++b) {
+        beta[pos] = b;
+        count = compositions(total - b, m, beta, pos + 1, out, count);
+    }
+    return count;
+}
+
+/* Grundmann-Moeller rule of degree 2s+1 on the d-simplex.
+ * Points in barycentric coordinates (d+1 of them), weights summing to the
+ * volume of the unit simplex, 1/d!:
+ *   w_i = (-1)^i 2^{-2s} (2s+1+d-2i)^{2s+1} / (i! (2s+1+d-i)!),  i = 0..s,
+ *   points ((2 beta_0 + 1), ..., (2 beta_d + 1)) / (2s+1+d-2i), |beta| = s-i.
+ * Returns the number of points, or -1 if they do not fit.                 */
+int oracle_gm_rule(int dim, int s, double pts[][4], double *w)
+{
+    const int deg = 2 * s + 1;
+    int count = 0;
+    for (int i = 0; i <= s; ++i) {
+        int betas[ORACLE_MAX_QP][4], beta[4];
+        int nb = compositions(s - i, dim + 1, beta, 0, betas, 0);
+        if (count + nb > ORACLE_MAX_QP) return -1;
+        double wi = pow(2.0, -2.0 * s) * pow((double)(deg + dim - 2 * i), deg)
+                    / ((double)factorial(i) * (double)factorial(deg + dim - i));
+        if (i % 2) wi = -wi;
+        for (int k = 0; k < nb; ++k) {
+            for (int j = 0; j <= dim; ++j)
+                pts[count][j] = (2.0 * betas[k][j] + 1.0) / (double)(deg + dim - 2 * i);
+            for (int j = dim + 1; j < 4; ++j) pts[count][j] = 0.0;
+            w[count] = wi;
+            ++count;
+        }
+    }
+    return count;
+}
+
+/* ---- real instantiation ------------------------------------------------ */
+#define R double
+#define RE(v) (v)
+#define FN(name) name##_d
+#include "element.inc"
+#undef R
+#undef RE
+#undef FN
+
+/* ---- complex instantiation (complex-step derivatives) ------------------ */
+#define R double _Complex
+#define RE(v) creal(v)
+#define FN(name) name##_z
+#include "element.inc"
+#undef R
+#undef RE
+#undef FN
+
+static int local_size(int kind, int degree, int dim)
+{
+    int nv = dim + 1;
+    int nb = (degree == 1) ? nv : nv * (nv + 1) / 2;
+    return (kind == ORACLE_ELASTIC) ? dim * nb : nb;
+}
+
+static int check_args(int kind, int degree, int dim, int qs)
+{
+    if (kind != ORACLE_LAPLACE && kind != ORACLE_ELASTIC) return -1;
+    if (degree != 1 && degree != 2) return -1;
+    if (dim != 2 && dim != 3) return -1;
+    if (qs < 0 || qs > 4) return -1;
+    return 0;
+}
+
+/* One element: xv[a*dim + alpha].  Returns det V (d! x signed volume) in *detv. */
+int oracle_element(int kind, int degree, int dim, const double *xv, double mu,
+                   double lam, int qs, double *A, double *detv)
+{
+    if (check_args(kind, degree, dim, qs)) return -1;
+    double d = element_matrix_d(kind, degree, dim, xv, mu, lam, qs, A);
+    if (detv) *detv = d;
+    return 0;
+}
+
+/* All elements of a mesh.
+ *   coords: SoA double arrays x, y (, z) of length nv (z ignored in 2D)
+ *   conn:   [ne][dim+1] int32
+ *   mu,lam: [ne] (elasticity only; may be NULL otherwise)
+ *   A:      [ne][n][n] double output                                     */
+int oracle_integrate(int kind, int degree, int dim, int64_t nv,
+                     const double *x, const double *y, const double *z,
+                     int64_t ne, const int32_t *conn, const double *mu,
+                     const double *lam, int qs, double *A)
+{
+    if (check_args(kind, degree, dim, qs)) return -1;
+    if (kind == ORACLE_ELASTIC && (!mu || !lam)) return -1;
+    const int n = local_size(kind, degree, dim);
+    const double *X[3] = {x, y, z};
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|:bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double xv[12];
+        for (int a = 0; a <= dim; ++a) {
+            int32_t v = conn[e * (dim + 1) + a];
+            if (v < 0 || v >= nv) { bad = 1; v = 0; }
+            for (int al = 0; al < dim; ++al) xv[a * dim + al] = X[al][v];
+        }
+        double m = mu ? mu[e] : 0.0, l = lam ? lam[e] : 0.0;
+        element_matrix_d(kind, degree, dim, xv, m, l, qs, A + e * (int64_t)n * n);
+    }
+    return bad ? -2 : 0;
+}
+
+/* Complex-step gradient of L_e = sum_IJ dA_e[I][J] A_e[I][J] for each element.
+ *   gvert: [ne][dim+1][dim]  dL_e / d x_{conn[e][a]}[alpha]
+ *   gmu, glam: [ne] or NULL  dL_e / d mu_e, dL_e / d lambda_e
+ *   Lval: [ne] or NULL       L_e itself                                     */
+int oracle_gradient(int kind, int degree, int dim, int64_t nv,
+                    const double *x, const double *y, const double *z,
+                    int64_t ne, const int32_t *conn, const double *mu,
+                    const double *lam, const double *dA, int qs,
+                    double *gvert, double *gmu, double *glam, double *Lval)
+{
+    if (check_args(kind, degree, dim, qs)) return -1;
+    if (kind == ORACLE_ELASTIC && (!mu || !lam)) return -1;
+    const int n = local_size(kind, degree, dim);
+    const double *X[3] = {x, y, z};
+    const double h = 1e-30;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(|:bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double xv[12];
+        for (int a = 0; a <= dim; ++a) {
+            int32_t v = conn[e * (dim + 1) + a];
+            if (v < 0 || v >= nv) { bad = 1; v = 0; }
+            for (int al = 0; al < dim; ++al) xv[a * dim + al] = X[al][v];
+        }
+        const double *dAe = dA + e * (int64_t)n * n;
+        double m = mu ? mu[e] : 0.0, l = lam ? lam[e] : 0.0;
+        const int np = (dim + 1) * dim;
+        const int nparam = np + ((kind == ORACLE_ELASTIC) ? 2 : 0);
+        double _Complex Az[30 * 30];
+        for (int p = -1; p < nparam; ++p) {
+            double _Complex xz[12], mz = m, lz = l;
+            for (int k = 0; k < np; ++k) xz[k] = xv[k];
+            if (p >= 0 && p < np) xz[p] += h * I;
+            if (p == np) mz += h * I;
+            if (p == np + 1) lz += h * I;
+            element_matrix_z(kind, degree, dim, xz, mz, lz, qs, Az);
+            double _Complex L = 0.0;
+            for (int k = 0; k < n * n; ++k) L += dAe[k] * Az[k];
+            if (p < 0) {
+                if (Lval) Lval[e] = creal(L);
+            } else if (p < np) {
+                gvert[e * np + p] = cimag(L) / h;
+            } else if (p == np) {
+                if (gmu) gmu[e] = cimag(L) / h;
+            } else {
+                if (glam) glam[e] = cimag(L) / h;
+            }
+        }
+    }
+    return bad ? -2 : 0;
+}
