@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: batched element-matrix integration on one MI355X.
+
+Workload (the headline): 3D P1 linear elasticity on a 64^3-cell Kuhn-split unit
+cube, 1,572,864 tetrahedra with 1% flattened to aspect ratio ~1e3, lognormal
+per-element Lame coefficients, FP32 coordinates, inputs resident in HBM.
+
+One step = one forward integration of the whole mesh in plain FP32
+(gather -> J, J^-1, |J| -> geometric tensor -> G:K -> store).  ``value`` is
+element matrices per second over the K timed steps.  The same protocol is
+applied to further legs reported beside it: the split-precision MFMA forms,
+the adjoint (dL/dA -> dL/dx, dL/dmu, dL/dlambda), and the 3D P1 Laplacian.
+Kernel durations come from HIP events recorded on the launch stream around
+every launch.  The CPU baseline is the FP64 oracle on the same workload; its
+results also give the accuracy of every leg.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "element matrices/s + achieved GB/s, 3D P1 elasticity, plain FP32 vs MFMA form"
+
+
+def parse_args():
+    p = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--n", type=int, default=64, help="cells per side of the cube")
+    p.add_argument("--legs", default="all", help="'all' or 'fp32' (headline only)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def forward_bytes(E: int, n_vertices: int, n: int, dim: int, coeffs: bool, coord_bytes=4):
+    """Compulsory HBM bytes of one forward pass: connectivity, coefficients and
+    the output once per element, vertex coordinates once per vertex."""
+    per_elem = 4 * (dim + 1) + (8 if coeffs else 0) + 4 * n * n
+    return E * per_elem + n_vertices * dim * coord_bytes
+
+
+def adjoint_bytes(E: int, n_vertices: int, n: int, dim: int, coeffs: bool):
+    """dA, connectivity, coefficients and their gradients per element; vertex
+    coordinates read once and the vertex gradient read and written once."""
+    per_elem = 4 * n * n + 4 * (dim + 1) + (16 if coeffs else 0)
+    return E * per_elem + n_vertices * dim * 4 * 3
+
+
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_leg(fn, steps: int, warmup: int, name: str = ""):
+    import torch
+    progress(f"leg {name}: {warmup} warmup + {steps} timed steps")
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record()
+        fn()
+        e.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = sorted(s.elapsed_time(e) for s, e in ev)
+    return {
+        "wall_ms_per_step": (t1 - t0) * 1e3 / steps,
+        "kernel_ms_mean": sum(d) / len(d),
+        "kernel_ms_median": d[len(d) // 2],
+        "kernel_ms_p10": d[int(0.1 * (len(d) - 1))],
+        "kernel_ms_p90": d[int(0.9 * (len(d) - 1))],
+    }
+
+
+def element_errors(A_gpu, A_orc):
+    import numpy as np
+    E = A_orc.shape[0]
+    d = np.abs(A_gpu.reshape(E, -1).astype(np.float64) - A_orc.reshape(E, -1)).max(axis=1)
+    return d / np.abs(A_orc.reshape(E, -1)).max(axis=1)
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the element integration has no "
+              "cross-GPU step here); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_1103_0066_amd as fei
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    progress("generating the workload")
+    w = meshgen.elast3d_adjoint(args.n)
+    m = w.mesh
+    E, Nv = m.n_elements, m.n_vertices
+    coords = torch.from_numpy(m.soa()).to(dev)
+    conn = torch.from_numpy(m.conn).to(dev)
+    mu = torch.from_numpy(w.mu).to(dev)
+    lam = torch.from_numpy(w.lam).to(dev)
+    A = torch.empty((E, 12, 12), dtype=torch.float32, device=dev)
+    fwd_bytes = forward_bytes(E, Nv, 12, 3, True)
+
+    def fwd(prec):
+        return lambda: fei.integrate(coords, conn, "elastic_p1", mu, lam, precision=prec, out=A)
+
+    # ---- headline: plain FP32 forward -------------------------------------
+    head = time_leg(fwd("fp32"), args.steps, args.warmup, "fp32")
+    ms = head["wall_ms_per_step"]
+    achieved = fwd_bytes / (head["kernel_ms_mean"] * 1e-3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": E / (ms * 1e-3),
+        "unit": "element matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name.replace("adjoint of ", ""), "elements": E,
+                   "vertices": Nv, "precision": "fp32", "tau": 100.0,
+                   "algorithmic_bytes_per_step": fwd_bytes},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "fwd_fma_kernel<elastic_p1, 3, float>",
+                     "kernel_ms_mean": head["kernel_ms_mean"]},
+    }
+    legs = {"fp32": dict(head, gbs=achieved, elements_per_s=E / (head["kernel_ms_mean"] * 1e-3))}
+    outputs = {}
+    if args.legs == "all":
+        outputs["fp32"] = A[:].cpu().numpy() if not args.no_cpu_baseline else None
+        for prec in ("fp16x2", "bf16x2", "bf16x3"):
+            r = time_leg(fwd(prec), args.steps, args.warmup, prec)
+            gbs = fwd_bytes / (r["kernel_ms_mean"] * 1e-3) / 1e9
+            legs[prec] = dict(r, gbs=gbs, frac=gbs / HBM_PEAK_GBS,
+                              elements_per_s=E / (r["kernel_ms_mean"] * 1e-3),
+                              speedup_vs_fp32=head["kernel_ms_mean"] / r["kernel_ms_mean"])
+            if not args.no_cpu_baseline:
+                outputs[prec] = A.cpu().numpy()
+        # adjoint of the same workload
+        dA = torch.from_numpy(w.dA).to(dev)
+        dc = torch.zeros((3, Nv), dtype=torch.float32, device=dev)
+        dmu = torch.empty(E, dtype=torch.float32, device=dev)
+        dlam = torch.empty(E, dtype=torch.float32, device=dev)
+        def adj():
+            fei.integrate_adjoint(coords, conn, "elastic_p1", dA, mu, lam, dcoords=dc,
+                                  dmu=dmu, dlam=dlam)
+        r = time_leg(adj, args.steps, args.warmup, "adjoint_fp32")
+        ab = adjoint_bytes(E, Nv, 12, 3, True)
+        gbs = ab / (r["kernel_ms_mean"] * 1e-3) / 1e9
+        legs["adjoint_fp32"] = dict(r, gbs=gbs, frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=ab,
+                                    elements_per_s=E / (r["kernel_ms_mean"] * 1e-3))
+        # 3D P1 Laplacian on the unflattened cube
+        wl = meshgen.lap3d(args.n)
+        cl = torch.from_numpy(wl.mesh.soa()).to(dev)
+        kl = torch.from_numpy(wl.mesh.conn).to(dev)
+        Al = torch.empty((wl.mesh.n_elements, 4, 4), dtype=torch.float32, device=dev)
+        lb = forward_bytes(wl.mesh.n_elements, wl.mesh.n_vertices, 4, 3, False)
+        for prec in ("fp32", "fp16x2"):
+            r = time_leg(lambda: fei.integrate(cl, kl, "laplace_p1", precision=prec, out=Al),
+                         args.steps, args.warmup, f"laplace3d_{prec}")
+            gbs = lb / (r["kernel_ms_mean"] * 1e-3) / 1e9
+            legs[f"laplace3d_{prec}"] = dict(
+                r, gbs=gbs, frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=lb,
+                elements_per_s=wl.mesh.n_elements / (r["kernel_ms_mean"] * 1e-3),
+                note="129 MB working set fits the 256 MB MALL: GB/s here is not HBM-only")
+    result["legs"] = legs
+
+    # ---- CPU baseline: the FP64 oracle on the same workload ----------------
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+        progress(f"cpu baseline: FP64 oracle on {E} elements, {threads} threads")
+        t0 = time.perf_counter()
+        Ao = oracle.integrate("elastic_p1", m.coords, m.conn, w.mu, w.lam)
+        t1 = time.perf_counter()
+        result["cpu_baseline"] = {
+            "value": E / (t1 - t0), "unit": "element matrices/s", "cores": min(threads, cores),
+            "kind": "oracle",
+            "sample": f"the whole workload once ({E} elements), FP64 quadrature, "
+                      f"OpenMP over elements, {t1 - t0:.2f} s wall"}
+        acc = {}
+        for prec, Ag in outputs.items():
+            if Ag is None:
+                continue
+            err = element_errors(Ag, Ao)
+            acc[prec] = {"max": float(err.max()), "p99_9": float(np.quantile(err, 0.999)),
+                         "median": float(np.median(err))}
+        result["accuracy_vs_oracle"] = acc
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

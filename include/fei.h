@@ -1,0 +1,203 @@
+/* fei.h -- batched finite-element element-matrix integration on MI355X (gfx950).
+ *
+ * The library computes, for every simplex e of a mesh, the dense element
+ * matrix of a bilinear form as the tensor contraction of the paper
+ * "Finite Element Integration on GPUs" (Knepley & Terrel), Sec. 3, eq. 1:
+ *
+ *     A_e = G_e : K
+ *
+ * K (the reference or "analytic" tensor, eq. 7) depends only on the form and
+ * the reference simplex and is precomputed once per form (Sec. 3.1, last
+ * paragraph).  G_e (the geometric tensor, eq. 8) is formed inside the kernels
+ * from the element's vertex coordinates: the Jacobian J, its inverse and
+ * |det J|, and, for elasticity, the element's Lame coefficients.
+ *
+ * Forms (affine simplices, dim = 2 or 3):
+ *   FEI_LAPLACE_P1  A_ij = int grad phi_i . grad phi_j           (Sec. 3, eqs. 2-8)
+ *   FEI_ELASTIC_P1  A_IJ = int 2 mu eps(Phi_I):eps(Phi_J)
+ *                             + lambda div Phi_I div Phi_J        (Sec. 3, eqs. 9-15,
+ *                   with per-element Lame mu, lambda; mu = 1/2, lambda = 0 is the
+ *                   form of eq. 24)
+ *   FEI_LAPLACE_P2  as FEI_LAPLACE_P1 with the quadratic Lagrange basis
+ *
+ * Conventions shared by every entry point:
+ *   - Reference simplex: vertex 0 at the origin, vertex m+1 at e_m.  The
+ *     element's vertex conn[e][0] is the origin of J:
+ *     J[alpha][m] = x_{conn[e][m+1]}[alpha] - x_{conn[e][0]}[alpha].
+ *   - Element matrix size n: P1 Laplacian dim+1; P1 elasticity dim*(dim+1);
+ *     P2 Laplacian (dim+1)(dim+2)/2.  Vector DOFs are node-major, I = dim*a + c.
+ *     P2 DOFs: the dim+1 vertices, then edges (0,1),(0,2),..,(0,dim),(1,2),..
+ *   - Output A is row-major [E][n][n] FP32 (symmetric, so equally column-major).
+ *   - All mesh, coefficient and output arrays are DEVICE memory owned by the
+ *     caller.  Entry points that take a stream enqueue work on it and return
+ *     without synchronising; outputs are valid once the stream reaches them.
+ *   - |det J| is used for the volume, so either orientation integrates
+ *     correctly.  An element with det J == 0 yields Inf/NaN entries (IEEE) and
+ *     is counted (see fei_options.counters); the call still succeeds.
+ *
+ * Errors: every int-returning call returns FEI_OK (0) or a negative status.
+ * On error nothing is enqueued and no output is written.  fei_last_error()
+ * returns a thread-local message for the last failing call.  No entry point
+ * throws, aborts or exits.
+ */
+#ifndef FEI_H
+#define FEI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEI_ABI_VERSION 1
+
+enum fei_status {
+    FEI_OK = 0,
+    FEI_EINVAL = -1,      /* bad argument: null/misaligned pointer, bad form, dim, dtype, size */
+    FEI_EDEVICE = -2,     /* a HIP call failed; message in fei_last_error() */
+    FEI_ENOMEM = -3,      /* host or device allocation failed (plans only) */
+    FEI_EUNSUPPORTED = -4 /* valid request this build has no kernel for */
+};
+
+enum fei_form {
+    FEI_LAPLACE_P1 = 1,
+    FEI_ELASTIC_P1 = 2,
+    FEI_LAPLACE_P2 = 3
+};
+
+enum fei_dtype { FEI_F32 = 0, FEI_F64 = 1 };
+
+/* Arithmetic of the G:K contraction.  Geometry (J, J^-1, |J|, G) is always
+ * FP32, or FP64 for FP64 coordinates and for elements flagged by the quality
+ * test below.
+ *   FEI_PREC_FP32    FP32 fused multiply-adds.
+ *   FEI_PREC_FP16X2  MFMA: G split into FP16 hi + lo after per-element
+ *                    power-of-two scaling; K is exact in FP16; FP32 accumulate.
+ *   FEI_PREC_BF16X2  MFMA: G split into BF16 hi + lo (about 16 bits).
+ *   FEI_PREC_BF16X3  MFMA: G split into three BF16 terms (about 24 bits).   */
+enum fei_precision {
+    FEI_PREC_FP32 = 0,
+    FEI_PREC_FP16X2 = 1,
+    FEI_PREC_BF16X2 = 2,
+    FEI_PREC_BF16X3 = 3
+};
+
+/* Layouts of the reference tensor returned by fei_reference_tensor.
+ *   FEI_LAYOUT_BLOCK   K[i][j][mu][nu] = int_ref dphi_i/dxi_mu dphi_j/dxi_nu
+ *                      (eq. 7), [nb][nb][dim][dim] over the SCALAR basis of
+ *                      the form (for elasticity the vector element's tensor
+ *                      is this one times delta_cc' delta_dd', eq. 14).
+ *   FEI_LAYOUT_FOLDED  the integer-valued matrix Kf[g][n*n] the kernels use:
+ *                      A_e = sum_g Gf_e[g] Kf[g][:], where Gf_e holds the g
+ *                      unique entries of the symmetric geometric tensor times
+ *                      fei_reference_scale(form, dim).                        */
+enum fei_layout { FEI_LAYOUT_BLOCK = 0, FEI_LAYOUT_FOLDED = 1 };
+
+typedef struct fei_mesh {
+    int32_t dim;            /* 2 or 3 */
+    int32_t coord_dtype;    /* FEI_F32 or FEI_F64 */
+    int64_t n_vertices;     /* >= 1 unless n_elements == 0 */
+    int64_t n_elements;     /* >= 0 */
+    const void *x;          /* device [n_vertices] coordinates (SoA) */
+    const void *y;
+    const void *z;          /* NULL when dim == 2 */
+    const int32_t *conn;    /* device [n_elements][dim+1], 0 <= v < n_vertices */
+} fei_mesh;
+
+typedef struct fei_options {
+    int32_t precision;      /* enum fei_precision */
+    float tau;              /* quality threshold: an element whose
+                               kappa = |J|_F |adj J|_F / |det J| (computed in
+                               FP32) exceeds tau takes the FP64 geometry path.
+                               <= 0 forces FP64 for every element; +Inf never. */
+    int32_t *counters;      /* optional device int32[2], accumulated (+=):
+                               [0] elements that took the FP64 path,
+                               [1] elements with det J == 0.  NULL: none. */
+    int32_t tile;           /* elements per workgroup; <= 0 picks the default */
+    int32_t reserved[4];    /* must be zero */
+} fei_options;
+
+/* Version of this ABI (FEI_ABI_VERSION). */
+int fei_abi_version(void);
+
+/* Static description of a status code. */
+const char *fei_status_str(int status);
+
+/* Thread-local message describing the last failing call on this thread. */
+const char *fei_last_error(void);
+
+/* Fills *opt with defaults: FP32, tau = 100, no counters, default tile. */
+int fei_options_default(fei_options *opt);
+
+/* Element matrix size n for (form, dim), or FEI_EINVAL. */
+int fei_local_size(int form, int dim);
+
+/* The reference tensor K of (form, dim) in the given layout, into HOST memory.
+ * With K == NULL only *len (number of floats) is written.  For the folded
+ * layout *g_out (if not NULL) receives g.  Host-only: needs no device.
+ * Sec. 3, eq. 7 (block layout) and eq. 1 (the contraction the folded layout
+ * serves).                                                                   */
+int fei_reference_tensor(int form, int dim, int layout, float *K, int64_t *len,
+                         int32_t *g_out);
+
+/* Scale s with Gf = s * |det J| * (unique entries of J^-1 J^-T [elasticity:
+ * of its Lame analogue]); the folded K is K_block / (s * ... ) made integral. */
+double fei_reference_scale(int form, int dim);
+
+/* Forward: A[e] = G_e : K for every element (Sec. 3, eqs. 1, 6-8, 14-15).
+ *   m        mesh (host struct, device arrays)
+ *   form     enum fei_form
+ *   mu, lam  device [E] FP32 Lame coefficients for FEI_ELASTIC_P1, NULL otherwise
+ *   A        device [E][n][n] FP32, 16-byte aligned, overwritten
+ *   opt      NULL for defaults
+ *   stream   hipStream_t (NULL: the null stream)                            */
+int fei_integrate(const fei_mesh *m, int form, const float *mu, const float *lam,
+                  float *A, const fei_options *opt, void *stream);
+
+/* Adjoint of fei_integrate for L = sum_e <dA_e, A_e> (the reverse of the
+ * chain A_e <- G_e <- (J^-1, |J|) <- vertex coordinates, Lame coefficients),
+ * with G recomputed from the mesh rather than stored.
+ *   dA          device [E][n][n] FP32, any (not necessarily symmetric) values
+ *   dx, dy, dz  device [n_vertices] FP32: dL/dx is ADDED (+=) by FP32 atomics;
+ *               dz is NULL in 2D.  The caller zeroes them first if needed.
+ *               Summation order is not deterministic.
+ *   dmu, dlam   device [E] FP32, overwritten (FEI_ELASTIC_P1 only; NULL skips)
+ * Only FEI_PREC_FP32 is accepted for the adjoint.                           */
+int fei_integrate_adjoint(const fei_mesh *m, int form, const float *mu,
+                          const float *lam, const float *dA, float *dx, float *dy,
+                          float *dz, float *dmu, float *dlam,
+                          const fei_options *opt, void *stream);
+
+/* Checks conn against n_vertices on the device and returns the number of
+ * out-of-range entries in *n_bad.  Synchronises the stream.                 */
+int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream);
+
+/* ---- heterogeneous batches ------------------------------------------------
+ * Many meshes and forms integrated by one persistent launch captured in a HIP
+ * graph (the paper's element batches, Sec. 4, applied across meshes).  The
+ * plan owns only its descriptor table and graph; every pointer in the items
+ * is caller memory that must outlive the plan.                              */
+typedef struct fei_batch_item {
+    fei_mesh mesh;
+    int32_t form;
+    int32_t pad_;
+    const float *mu, *lam;  /* elasticity only */
+    float *A;               /* forward output [E][n][n] */
+    const float *dA;        /* adjoint input (NULL if the adjoint is not used) */
+    float *dx, *dy, *dz;    /* adjoint vertex gradients (accumulated) */
+    float *dmu, *dlam;      /* adjoint coefficient gradients (overwritten) */
+} fei_batch_item;
+
+typedef struct fei_batch fei_batch;
+
+int fei_batch_create(const fei_batch_item *items, int n_items,
+                     const fei_options *opt, fei_batch **out);
+int fei_batch_run(fei_batch *b, void *stream);
+int fei_batch_run_adjoint(fei_batch *b, void *stream);
+int fei_batch_destroy(fei_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEI_H */

@@ -1,0 +1,101 @@
+"""ctypes view of libfei.so (include/fei.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfei.so")
+
+FEI_OK = 0
+FEI_EINVAL = -1
+FEI_EDEVICE = -2
+FEI_ENOMEM = -3
+FEI_EUNSUPPORTED = -4
+
+FORMS = {"laplace_p1": 1, "elastic_p1": 2, "laplace_p2": 3}
+PRECISIONS = {"fp32": 0, "fp16x2": 1, "bf16x2": 2, "bf16x3": 3}
+LAYOUT_BLOCK = 0
+LAYOUT_FOLDED = 1
+F32 = 0
+F64 = 1
+
+EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_default",
+           "fei_local_size", "fei_reference_tensor", "fei_reference_scale", "fei_integrate",
+           "fei_integrate_adjoint", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
+           "fei_batch_run_adjoint", "fei_batch_destroy")
+
+
+class FeiMesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("coord_dtype", ctypes.c_int32),
+                ("n_vertices", ctypes.c_int64), ("n_elements", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("conn", ctypes.c_void_p)]
+
+
+class FeiOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("tau", ctypes.c_float),
+                ("counters", ctypes.c_void_p), ("tile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class FeiBatchItem(ctypes.Structure):
+    _fields_ = [("mesh", FeiMesh), ("form", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("mu", ctypes.c_void_p), ("lam", ctypes.c_void_p), ("A", ctypes.c_void_p),
+                ("dA", ctypes.c_void_p), ("dx", ctypes.c_void_p), ("dy", ctypes.c_void_p),
+                ("dz", ctypes.c_void_p), ("dmu", ctypes.c_void_p), ("dlam", ctypes.c_void_p)]
+
+
+class FeiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fei status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libfei.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python paper_1103_0066_amd/build.py or __graft_entry__.build()). "
+            "There is no fallback implementation.")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32p = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.fei_abi_version.restype = ctypes.c_int
+    lib.fei_status_str.restype = ctypes.c_char_p
+    lib.fei_status_str.argtypes = [ctypes.c_int]
+    lib.fei_last_error.restype = ctypes.c_char_p
+    lib.fei_options_default.argtypes = [ctypes.POINTER(FeiOptions)]
+    lib.fei_local_size.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fei_reference_tensor.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                         ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    lib.fei_reference_scale.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fei_reference_scale.restype = ctypes.c_double
+    lib.fei_integrate.argtypes = [ctypes.POINTER(FeiMesh), ctypes.c_int, f32p, f32p, f32p,
+                                  ctypes.POINTER(FeiOptions), vp]
+    lib.fei_integrate_adjoint.argtypes = [ctypes.POINTER(FeiMesh), ctypes.c_int, f32p, f32p,
+                                          f32p, f32p, f32p, f32p, f32p, f32p,
+                                          ctypes.POINTER(FeiOptions), vp]
+    lib.fei_validate_mesh.argtypes = [ctypes.POINTER(FeiMesh), ctypes.POINTER(i64), vp]
+    lib.fei_batch_create.argtypes = [ctypes.POINTER(FeiBatchItem), ctypes.c_int,
+                                     ctypes.POINTER(FeiOptions), ctypes.POINTER(vp)]
+    lib.fei_batch_run.argtypes = [vp, vp]
+    lib.fei_batch_run_adjoint.argtypes = [vp, vp]
+    lib.fei_batch_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        getattr(lib, name)
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> int:
+    if status < 0:
+        lib = load()
+        raise FeiError(status, lib.fei_last_error().decode())
+    return status

@@ -1,0 +1,68 @@
+"""Heterogeneous batches: many meshes and forms in one graph-captured launch."""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional
+
+import torch
+
+from . import _lib
+
+
+class Batch:
+    """A plan over several (mesh, form) items (see fei_batch_create).
+
+    Each item is a dict with keys coords, conn, form, and optionally mu, lam,
+    A (output; allocated if absent), dA, dcoords, dmu, dlam (adjoint).
+    Every tensor must stay alive while the plan exists.
+    """
+
+    def __init__(self, items: List[dict], precision: str = "fp32", tau: float = 100.0):
+        from . import _mesh, _options, local_size, _form_id, _ptr
+        lib = _lib.load()
+        self._items = items
+        arr = (_lib.FeiBatchItem * len(items))()
+        for k, it in enumerate(items):
+            coords, conn, form = it["coords"], it["conn"], it["form"]
+            m = _mesh(coords, conn)
+            n = local_size(form, m.dim)
+            if it.get("A") is None:
+                it["A"] = torch.empty((m.n_elements, n, n), dtype=torch.float32,
+                                      device=coords.device)
+            b = arr[k]
+            b.mesh = m
+            b.form = _form_id(form)
+            b.mu = _ptr(it.get("mu"))
+            b.lam = _ptr(it.get("lam"))
+            b.A = _ptr(it["A"])
+            b.dA = _ptr(it.get("dA"))
+            dc = it.get("dcoords")
+            b.dx = dc[0].data_ptr() if dc is not None else None
+            b.dy = dc[1].data_ptr() if dc is not None else None
+            b.dz = dc[2].data_ptr() if (dc is not None and m.dim == 3) else None
+            b.dmu = _ptr(it.get("dmu"))
+            b.dlam = _ptr(it.get("dlam"))
+        self._arr = arr
+        o = _options(precision, tau, None)
+        h = ctypes.c_void_p()
+        _lib.check(lib.fei_batch_create(arr, len(items), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream: Optional[torch.cuda.Stream] = None):
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        _lib.check(_lib.load().fei_batch_run(self._h, s))
+
+    def run_adjoint(self, stream: Optional[torch.cuda.Stream] = None):
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        _lib.check(_lib.load().fei_batch_run_adjoint(self._h, s))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().fei_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,308 @@
+// Host side of libfei: argument validation, kernel dispatch, status codes.
+// Implements every entry point declared in include/fei.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fei.h"
+#include "params.h"
+#include "shapes.h"
+
+using namespace fei;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(FEI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+bool valid_form(int form) { return form == FEI_LAPLACE_P1 || form == FEI_ELASTIC_P1 || form == FEI_LAPLACE_P2; }
+
+int local_size(int form, int dim)
+{
+    if (!valid_form(form) || (dim != 2 && dim != 3)) return -1;
+    const int nb = (form == FEI_LAPLACE_P2) ? (dim + 1) * (dim + 2) / 2 : dim + 1;
+    return form == FEI_ELASTIC_P1 ? dim * nb : nb;
+}
+
+fei_options defaults()
+{
+    fei_options o;
+    std::memset(&o, 0, sizeof o);
+    o.precision = FEI_PREC_FP32;
+    o.tau = 100.0f;
+    o.counters = nullptr;
+    o.tile = 0;
+    return o;
+}
+
+int check_options(const fei_options &o)
+{
+    if (o.precision < FEI_PREC_FP32 || o.precision > FEI_PREC_BF16X3)
+        return fail(FEI_EINVAL, "unknown precision %d", o.precision);
+    if (std::isnan(o.tau)) return fail(FEI_EINVAL, "tau is NaN");
+    for (int r : o.reserved)
+        if (r != 0) return fail(FEI_EINVAL, "fei_options.reserved must be zero");
+    if (o.counters && !aligned(o.counters, 4)) return fail(FEI_EINVAL, "counters misaligned");
+    return FEI_OK;
+}
+
+float tau2_of(float tau)
+{
+    if (tau <= 0.0f) return -1.0f;   // every element takes the FP64 path
+    return tau * tau;                // +Inf stays +Inf
+}
+
+// Validates the mesh struct and fills the kernel view.
+int check_mesh(const fei_mesh *m, MeshView &mv)
+{
+    if (!m) return fail(FEI_EINVAL, "mesh is NULL");
+    if (m->dim != 2 && m->dim != 3) return fail(FEI_EINVAL, "dim must be 2 or 3 (got %d)", m->dim);
+    if (m->coord_dtype != FEI_F32 && m->coord_dtype != FEI_F64)
+        return fail(FEI_EINVAL, "unknown coord_dtype %d", m->coord_dtype);
+    if (m->n_elements < 0) return fail(FEI_EINVAL, "n_elements < 0");
+    if (m->n_elements > 0) {
+        if (m->n_vertices < 1) return fail(FEI_EINVAL, "n_vertices < 1");
+        if (m->n_vertices > int64_t(INT32_MAX) + 1)
+            return fail(FEI_EINVAL, "n_vertices exceeds the int32 connectivity range");
+        const size_t cs = m->coord_dtype == FEI_F64 ? 8 : 4;
+        if (!m->x || !m->y) return fail(FEI_EINVAL, "x or y is NULL");
+        if (m->dim == 3 && !m->z) return fail(FEI_EINVAL, "z is NULL for a 3D mesh");
+        if (!aligned(m->x, cs) || !aligned(m->y, cs) || (m->dim == 3 && !aligned(m->z, cs)))
+            return fail(FEI_EINVAL, "coordinate arrays misaligned");
+        if (!m->conn) return fail(FEI_EINVAL, "conn is NULL");
+        if (!aligned(m->conn, m->dim == 3 ? 16 : 4))
+            return fail(FEI_EINVAL, "conn must be %d-byte aligned", m->dim == 3 ? 16 : 4);
+    }
+    mv.x = m->x;
+    mv.y = m->y;
+    mv.z = m->dim == 3 ? m->z : nullptr;
+    mv.conn = m->conn;
+    mv.n_elements = m->n_elements;
+    mv.n_vertices = m->n_vertices;
+    return FEI_OK;
+}
+
+int check_coeffs(int form, const float *mu, const float *lam, int64_t E)
+{
+    if (form == FEI_ELASTIC_P1) {
+        if (E > 0 && (!mu || !lam)) return fail(FEI_EINVAL, "elasticity needs mu and lam");
+        if ((mu && !aligned(mu, 4)) || (lam && !aligned(lam, 4)))
+            return fail(FEI_EINVAL, "mu/lam misaligned");
+    } else if (mu || lam) {
+        return fail(FEI_EINVAL, "mu/lam must be NULL for a Laplacian form");
+    }
+    return FEI_OK;
+}
+
+// K of (form, dim) through the same functions the kernels' tables come from.
+template <typename F>
+int with_traits(int form, int dim, F &&f)
+{
+    if (dim == 2) {
+        if (form == FEI_LAPLACE_P1) return f(Traits<LAP1, 2>{});
+        if (form == FEI_ELASTIC_P1) return f(Traits<ELA1, 2>{});
+        if (form == FEI_LAPLACE_P2) return f(Traits<LAP2, 2>{});
+    } else if (dim == 3) {
+        if (form == FEI_LAPLACE_P1) return f(Traits<LAP1, 3>{});
+        if (form == FEI_ELASTIC_P1) return f(Traits<ELA1, 3>{});
+        if (form == FEI_LAPLACE_P2) return f(Traits<LAP2, 3>{});
+    }
+    return fail(FEI_EINVAL, "bad form %d or dim %d", form, dim);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fei_abi_version(void) { return FEI_ABI_VERSION; }
+
+const char *fei_status_str(int status)
+{
+    switch (status) {
+    case FEI_OK: return "success";
+    case FEI_EINVAL: return "invalid argument";
+    case FEI_EDEVICE: return "device (HIP) error";
+    case FEI_ENOMEM: return "out of memory";
+    case FEI_EUNSUPPORTED: return "unsupported variant";
+    default: return "unknown status";
+    }
+}
+
+const char *fei_last_error(void) { return g_last_error.c_str(); }
+
+int fei_options_default(fei_options *opt)
+{
+    if (!opt) return fail(FEI_EINVAL, "opt is NULL");
+    *opt = defaults();
+    return FEI_OK;
+}
+
+int fei_local_size(int form, int dim)
+{
+    const int n = local_size(form, dim);
+    return n < 0 ? fail(FEI_EINVAL, "bad form %d or dim %d", form, dim) : n;
+}
+
+double fei_reference_scale(int form, int dim)
+{
+    double s = 0.0;
+    with_traits(form, dim, [&](auto t) {
+        s = decltype(t)::SCALE;
+        return FEI_OK;
+    });
+    return s;
+}
+
+int fei_reference_tensor(int form, int dim, int layout, float *K, int64_t *len, int32_t *g_out)
+{
+    if (!len) return fail(FEI_EINVAL, "len is NULL");
+    if (layout != FEI_LAYOUT_BLOCK && layout != FEI_LAYOUT_FOLDED)
+        return fail(FEI_EINVAL, "unknown layout %d", layout);
+    return with_traits(form, dim, [&](auto t) {
+        using T = decltype(t);
+        const int F = form == FEI_LAPLACE_P1 ? LAP1 : form == FEI_ELASTIC_P1 ? ELA1 : LAP2;
+        if (layout == FEI_LAYOUT_BLOCK) {
+            *len = int64_t(T::NB) * T::NB * dim * dim;
+            if (g_out) *g_out = T::G;
+            if (!K) return FEI_OK;
+            // eq. 7 values: the integer tensor times vol_ref / KDEN
+            for (int i = 0; i < T::NB; ++i)
+                for (int j = 0; j < T::NB; ++j)
+                    for (int mu = 0; mu < dim; ++mu)
+                        for (int nu = 0; nu < dim; ++nu)
+                            K[((i * T::NB + j) * dim + mu) * dim + nu] =
+                                float(double(kblock(F, dim, i, j, mu, nu)) * T::SCALE);
+            return FEI_OK;
+        }
+        const int nn = T::N * T::N;
+        *len = int64_t(T::G) * nn;
+        if (g_out) *g_out = T::G;
+        if (!K) return FEI_OK;
+        for (int g = 0; g < T::G; ++g) {
+            int p = 0, q = 0;
+            sym_pair(T::GD, g, p, q);
+            for (int I = 0; I < T::N; ++I)
+                for (int J = 0; J < T::N; ++J)
+                    K[int64_t(g) * nn + I * T::N + J] = float(kfolded(F, dim, p, q, I, J));
+        }
+        return FEI_OK;
+    });
+}
+
+int fei_integrate(const fei_mesh *m, int form, const float *mu, const float *lam, float *A,
+                  const fei_options *opt, void *stream)
+{
+    MeshView mv;
+    int rc = check_mesh(m, mv);
+    if (rc) return rc;
+    if (!valid_form(form)) return fail(FEI_EINVAL, "unknown form %d", form);
+    fei_options o = opt ? *opt : defaults();
+    if ((rc = check_options(o))) return rc;
+    if ((rc = check_coeffs(form, mu, lam, m->n_elements))) return rc;
+    if (m->n_elements == 0) return FEI_OK;
+    if (!A) return fail(FEI_EINVAL, "A is NULL");
+    if (!aligned(A, 16)) return fail(FEI_EINVAL, "A must be 16-byte aligned");
+    const Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision};
+    FwdLauncher launch = find_forward(v);
+    if (!launch) return fail(FEI_EUNSUPPORTED, "no forward kernel for this variant");
+    FwdParams p;
+    p.m = mv;
+    p.mu = mu;
+    p.lam = lam;
+    p.A = A;
+    p.counters = o.counters;
+    p.tau2 = tau2_of(o.tau);
+    hipError_t e = launch(p, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return FEI_OK;
+}
+
+int fei_integrate_adjoint(const fei_mesh *m, int form, const float *mu, const float *lam,
+                          const float *dA, float *dx, float *dy, float *dz, float *dmu,
+                          float *dlam, const fei_options *opt, void *stream)
+{
+    MeshView mv;
+    int rc = check_mesh(m, mv);
+    if (rc) return rc;
+    if (!valid_form(form)) return fail(FEI_EINVAL, "unknown form %d", form);
+    fei_options o = opt ? *opt : defaults();
+    if ((rc = check_options(o))) return rc;
+    if (o.precision != FEI_PREC_FP32)
+        return fail(FEI_EUNSUPPORTED, "the adjoint is FP32 only");
+    if ((rc = check_coeffs(form, mu, lam, m->n_elements))) return rc;
+    if (form != FEI_ELASTIC_P1 && (dmu || dlam))
+        return fail(FEI_EINVAL, "dmu/dlam must be NULL for a Laplacian form");
+    if (m->n_elements == 0) return FEI_OK;
+    if (!dA || !aligned(dA, 16)) return fail(FEI_EINVAL, "dA NULL or not 16-byte aligned");
+    if (!dx || !dy || (m->dim == 3 && !dz)) return fail(FEI_EINVAL, "dx/dy/dz missing");
+    if (!aligned(dx, 4) || !aligned(dy, 4) || (dz && !aligned(dz, 4)))
+        return fail(FEI_EINVAL, "dx/dy/dz misaligned");
+    const Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision};
+    AdjLauncher launch = find_adjoint(v);
+    if (!launch) return fail(FEI_EUNSUPPORTED, "no adjoint kernel for this variant");
+    AdjParams p;
+    p.m = mv;
+    p.mu = mu;
+    p.lam = lam;
+    p.dA = dA;
+    p.dx = dx;
+    p.dy = dy;
+    p.dz = m->dim == 3 ? dz : nullptr;
+    p.dmu = dmu;
+    p.dlam = dlam;
+    p.counters = o.counters;
+    p.tau2 = tau2_of(o.tau);
+    hipError_t e = launch(p, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    return FEI_OK;
+}
+
+int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream)
+{
+    MeshView mv;
+    int rc = check_mesh(m, mv);
+    if (rc) return rc;
+    if (!n_bad) return fail(FEI_EINVAL, "n_bad is NULL");
+    *n_bad = 0;
+    if (m->n_elements == 0) return FEI_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long *dev = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&dev), sizeof(unsigned long long), s);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+    unsigned long long host = 0;
+    if ((e = hipMemsetAsync(dev, 0, sizeof host, s)) == hipSuccess &&
+        (e = launch_validate(mv, m->dim, dev, s)) == hipSuccess &&
+        (e = hipMemcpyAsync(&host, dev, sizeof host, hipMemcpyDeviceToHost, s)) == hipSuccess)
+        e = hipStreamSynchronize(s);
+    hipError_t e2 = hipFreeAsync(dev, s);
+    if (e != hipSuccess) return hip_fail(e, "validate");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    *n_bad = int64_t(host);
+    return FEI_OK;
+}
+
+}  // extern "C"

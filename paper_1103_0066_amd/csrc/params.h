@@ -1,0 +1,56 @@
+// Kernel parameter blocks and launcher declarations shared by the host layer
+// (api.cpp) and the device code (kernels.hip).  Plain structs, no HIP types
+// beyond hipStream_t / hipError_t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fei {
+
+struct MeshView {
+    const void *x, *y, *z;     // SoA coordinates (float or double)
+    const int32_t *conn;       // [E][dim+1]
+    int64_t n_elements;
+    int64_t n_vertices;
+};
+
+struct FwdParams {
+    MeshView m;
+    const float *mu, *lam;     // elasticity only
+    float *A;                  // [E][n][n]
+    int32_t *counters;         // optional [2]
+    float tau2;                // squared quality threshold; < 0 forces FP64
+};
+
+struct AdjParams {
+    MeshView m;
+    const float *mu, *lam;
+    const float *dA;           // [E][n][n]
+    float *dx, *dy, *dz;       // [n_vertices], accumulated
+    float *dmu, *dlam;         // [E] or NULL
+    int32_t *counters;
+    float tau2;
+};
+
+// Kernel selection key.
+struct Variant {
+    int form;       // fei::Form
+    int dim;        // 2 or 3
+    int coord_f64;  // 0/1
+    int precision;  // fei_precision
+};
+
+using FwdLauncher = hipError_t (*)(const FwdParams &, hipStream_t);
+using AdjLauncher = hipError_t (*)(const AdjParams &, hipStream_t);
+
+// Returns NULL when no kernel exists for the variant.
+FwdLauncher find_forward(const Variant &v);
+AdjLauncher find_adjoint(const Variant &v);
+
+// Device-side connectivity check: writes the count of entries outside
+// [0, n_vertices) into *n_bad_dev (int64, zeroed by the kernel's caller).
+hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad_dev,
+                           hipStream_t s);
+
+}  // namespace fei

@@ -1,0 +1,71 @@
+// Compile-time shapes shared by the kernels and the table generator: MFMA
+// tiling of the folded contraction, 16-bit encodings of small integers and
+// the pair index of symmetric tensors.  Host and device.
+#pragma once
+
+#include "reftensor.h"
+
+namespace fei {
+
+enum Prec { P_FP32 = 0, P_FP16X2 = 1, P_BF16X2 = 2, P_BF16X3 = 3 };
+
+// MFMA form of A^T[entries][elements] = Kf^T[entries][g] Gf^T[g][elements]
+// with 16x16x32 tiles: M = entries (MT tiles), K = split Gf (KS steps of 32).
+template <int FORM, int DIM, int PREC>
+struct MfmaShape {
+    using T = Traits<FORM, DIM>;
+    static constexpr int NSPLIT = (PREC == P_BF16X3) ? 3 : 2;
+    static constexpr int KT = ((T::G * NSPLIT + 31) / 32) * 32;  // padded reduction length
+    static constexpr int KS = KT / 32;                           // MFMA k-steps
+    static constexpr int NN = T::N * T::N;
+    static constexpr int MT = (NN + 15) / 16;                    // M tiles of 16 entries
+    static constexpr int NFRAG = MT * KS * 64;                   // 16-byte lane fragments
+    static constexpr int BROW = KT + 8;                          // LDS row (halfs), padded
+};
+
+// Block reference tensor [NB][NB][DIM][DIM] (integer values, as float).
+template <int FORM, int DIM>
+struct KBlockTable {
+    float v[Traits<FORM, DIM>::NB * Traits<FORM, DIM>::NB * DIM * DIM];
+};
+
+// K fragments of the MFMA A operand in lane order: fragment
+// f = (t*KS + s)*64 + lane holds A[m][32 s + 8 (lane/16) + j], j = 0..7, with
+// m = 16 t + lane % 16 and A[m][k] = Kf[k mod g][m] for k < g*NSPLIT, else 0.
+template <int FORM, int DIM, int PREC>
+struct FragTable {
+    uint16_t v[MfmaShape<FORM, DIM, PREC>::NFRAG * 8];
+};
+
+FEI_HD constexpr void sym_pair(int gd, int gamma, int &p, int &q)
+{
+    for (int i = 0; i < gd; ++i)
+        for (int j = i; j < gd; ++j)
+            if (sym_index(gd, i, j) == gamma) { p = i; q = j; return; }
+    p = q = 0;
+}
+
+// 16-bit encodings of integers exactly representable in the format.
+inline uint16_t f16_bits_of_int(int v)
+{
+    if (v == 0) return 0;
+    unsigned s = v < 0 ? 1u : 0u;
+    unsigned a = v < 0 ? unsigned(-v) : unsigned(v);
+    int e = 0;
+    while ((a >> (e + 1)) != 0) ++e;
+    unsigned mant = (e <= 10) ? ((a << (10 - e)) & 0x3FFu) : ((a >> (e - 10)) & 0x3FFu);
+    return uint16_t((s << 15) | (unsigned(e + 15) << 10) | mant);
+}
+
+inline uint16_t bf16_bits_of_int(int v)
+{
+    if (v == 0) return 0;
+    unsigned s = v < 0 ? 1u : 0u;
+    unsigned a = v < 0 ? unsigned(-v) : unsigned(v);
+    int e = 0;
+    while ((a >> (e + 1)) != 0) ++e;
+    unsigned mant = (e <= 7) ? ((a << (7 - e)) & 0x7Fu) : ((a >> (e - 7)) & 0x7Fu);
+    return uint16_t((s << 15) | (unsigned(e + 127) << 7) | mant);
+}
+
+}  // namespace fei

@@ -1,0 +1,46 @@
+"""Shared helpers for the GPU parity tests (inputs to the device, error metrics)."""
+import numpy as np
+import torch
+
+# Per-element normwise tolerance against the FP64 oracle:
+#   max_ij |A_gpu - A_oracle| / max_ij |A_oracle|  <= TOL[precision]
+# FP32 and FP16x2 meet 1e-5; BF16x2 (about 16 significant bits in G) is held to
+# its stated bound 3e-5; BF16x3 (about 24 bits) to 1e-5.
+TOL = {"fp32": 1e-5, "fp16x2": 1e-5, "bf16x2": 3e-5, "bf16x3": 1e-5}
+
+# Adjoint: vertex gradients are sums of ~24 partially cancelling FP32 terms
+# added by atomics, judged against the sum of the magnitudes of the terms;
+# per-element coefficient gradients against the element's own scale.
+TOL_VERTEX = 1e-4
+TOL_COEFF = 1e-5
+
+
+def device():
+    return torch.device("cuda", 0)
+
+
+def mesh_to_device(mesh, dev=None):
+    dev = dev or device()
+    coords = torch.from_numpy(mesh.soa()).to(dev)
+    conn = torch.from_numpy(np.ascontiguousarray(mesh.conn)).to(dev)
+    return coords, conn
+
+
+def vec_to_device(a, dev=None):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev or device())
+
+
+def element_errors(A_gpu: np.ndarray, A_orc: np.ndarray) -> np.ndarray:
+    """Normwise error of every element."""
+    d = np.abs(A_gpu.astype(np.float64) - A_orc).reshape(len(A_orc), -1).max(axis=1)
+    s = np.abs(A_orc).reshape(len(A_orc), -1).max(axis=1)
+    return d / s
+
+
+def vertex_scale(gvert: np.ndarray, conn: np.ndarray, n_vertices: int) -> np.ndarray:
+    """Per vertex: sum over incident elements of |per-element contribution| (max over
+    components), the natural scale of an atomically accumulated vertex gradient."""
+    mag = np.abs(gvert).max(axis=2)                      # [E, dim+1]
+    s = np.zeros(n_vertices)
+    np.add.at(s, conn.ravel(), mag.ravel())
+    return s

@@ -1,0 +1,169 @@
+"""Adjoint parity: HIP adjoint against the oracle's complex-step gradients,
+central differences, invariants at full size, and the autograd wiring."""
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+from gpu_util import (TOL_COEFF, TOL_VERTEX, mesh_to_device, vec_to_device, vertex_scale)
+
+pytestmark = pytest.mark.gpu
+
+fei = pytest.importorskip("paper_1103_0066_amd")
+
+
+def _case(name):
+    if name == "lap2d_f64":
+        return meshgen.square_mesh(17, 0.2, 41, np.float64), "laplace_p1", None, None
+    if name == "lap3d":
+        return meshgen.cube_mesh(5, 5, 4, 0.15, 42), "laplace_p1", None, None
+    if name == "elast3d":
+        m = meshgen.flatten_elements(meshgen.cube_mesh(6, 5, 5, 0.15, 43), 9, 44)
+        mu, lam = meshgen.lame(m.n_elements, 45)
+        return m, "elastic_p1", mu, lam
+    if name == "elast2d":
+        m = meshgen.square_mesh(17, 0.2, 46, np.float32)
+        mu, lam = meshgen.lame(m.n_elements, 47)
+        return m, "elastic_p1", mu, lam
+    if name == "p2_3d":
+        return meshgen.cube_mesh(4, 4, 4, 0.15, 48), "laplace_p2", None, None
+    raise KeyError(name)
+
+
+def _gpu_adjoint(mesh, form, mu, lam, dA):
+    coords, conn = mesh_to_device(mesh)
+    dc, dmu, dlam = fei.integrate_adjoint(coords, conn, form, vec_to_device(dA),
+                                          vec_to_device(mu), vec_to_device(lam))
+    torch.cuda.synchronize()
+    g = dc.cpu().numpy().T.astype(np.float64)      # [N_v, dim]
+    return (g, None if dmu is None else dmu.cpu().numpy(),
+            None if dlam is None else dlam.cpu().numpy())
+
+
+def _check_against_oracle(mesh, form, mu, lam, dA, conn_sel=None):
+    g, dmu, dlam = _gpu_adjoint(mesh, form, mu, lam, dA)
+    gv, gm, gl, Le = oracle.gradient(form, mesh.coords, mesh.conn, dA, mu, lam)
+    go = oracle.vertex_gradient(gv, mesh.conn, mesh.n_vertices)
+    scale = vertex_scale(gv, mesh.conn, mesh.n_vertices)
+    used = scale > 0
+    verr = np.abs(g - go).max(axis=1)[used] / scale[used]
+    print(f"  vertex err max {verr.max():.3e}")
+    assert verr.max() <= TOL_VERTEX
+    if gm is not None:
+        merr = _coeff_errors(mesh.coords, mesh.conn, dA, dmu, dlam, gm, gl)
+        print(f"  coeff err max {merr.max():.3e}")
+        assert merr.max() <= TOL_COEFF
+    return g, go
+
+
+def _coeff_errors(coords, conn, dA, dmu, dlam, gm, gl):
+    """A is linear in (mu, lambda), so dL/dmu_e = <dA_e, A_e(mu=1, lambda=0)>; each
+    coefficient gradient is judged against sum |dA_e| |A_e(1, 0)| (resp. (0, 1)),
+    the scale of the sum it is made of."""
+    E = conn.shape[0]
+    one, zero = np.ones(E), np.zeros(E)
+    dA = np.asarray(dA, np.float64).reshape(E, -1)
+    Am = oracle.integrate("elastic_p1", coords, conn, one, zero).reshape(E, -1)
+    Al = oracle.integrate("elastic_p1", coords, conn, zero, one).reshape(E, -1)
+    sm = (np.abs(dA) * np.abs(Am)).sum(axis=1)
+    sl = (np.abs(dA) * np.abs(Al)).sum(axis=1)
+    return np.maximum(np.abs(dmu - gm) / sm, np.abs(dlam - gl) / sl)
+
+
+@pytest.mark.parametrize("case", ["lap2d_f64", "lap3d", "elast3d", "elast2d", "p2_3d"])
+def test_adjoint_matches_oracle(case):
+    mesh, form, mu, lam = _case(case)
+    n = fei.local_size(form, mesh.dim)
+    dA = meshgen.upstream(mesh.n_elements, n, 49)
+    print(f"[adjoint] {case} E={mesh.n_elements}", flush=True)
+    _check_against_oracle(mesh, form, mu, lam, dA)
+
+
+@pytest.mark.parametrize("flat", [False, True])
+def test_adjoint_fd_submesh(flat):
+    """The 48-tet sub-mesh: GPU vs the oracle gradient and FP64 central differences."""
+    w = meshgen.fd_submesh(flat)
+    m = w.mesh
+    g, go = _check_against_oracle(m, w.form, w.mu, w.lam, w.dA)
+    X = m.coords.astype(np.float64)
+    h = 1e-9 if flat else 1e-6 / 64
+
+    def L(Xp):
+        return float(np.sum(oracle.integrate(w.form, Xp, m.conn, w.mu, w.lam) * w.dA))
+    fd = np.zeros_like(X)
+    for v in range(m.n_vertices):
+        for a in range(3):
+            Xp = X.copy(); Xp[v, a] += h
+            Xm = X.copy(); Xm[v, a] -= h
+            fd[v, a] = (L(Xp) - L(Xm)) / (2 * h)
+    np.testing.assert_allclose(go, fd, rtol=0, atol=1e-7 * np.abs(fd).max())
+    np.testing.assert_allclose(g, fd, rtol=0, atol=TOL_VERTEX * np.abs(fd).max())
+
+
+def test_adjoint_accumulates_into_given_buffer():
+    mesh, form, mu, lam = _case("lap3d")
+    coords, conn = mesh_to_device(mesh)
+    dA = vec_to_device(meshgen.upstream(mesh.n_elements, 4, 50))
+    d1, _, _ = fei.integrate_adjoint(coords, conn, form, dA)
+    base = torch.full_like(d1, 0.5)
+    d2, _, _ = fei.integrate_adjoint(coords, conn, form, dA, dcoords=base.clone())
+    torch.testing.assert_close(d2 - 0.5, d1, rtol=0, atol=1e-5 * float(d1.abs().max()))
+
+
+def test_autograd_function_matches_adjoint():
+    mesh, form, mu, lam = _case("elast3d")
+    coords, conn = mesh_to_device(mesh)
+    c = coords.clone().requires_grad_(True)
+    m_ = vec_to_device(mu).requires_grad_(True)
+    l_ = vec_to_device(lam).requires_grad_(True)
+    A = fei.element_matrices(c, conn, form, m_, l_)
+    dA = vec_to_device(meshgen.upstream(mesh.n_elements, 12, 51))
+    (A * dA).sum().backward()
+    dc, dmu, dlam = fei.integrate_adjoint(coords, conn, form, dA, vec_to_device(mu),
+                                          vec_to_device(lam))
+    torch.testing.assert_close(c.grad, dc, rtol=0, atol=1e-4 * float(dc.abs().max()))
+    torch.testing.assert_close(m_.grad, dmu, rtol=0, atol=1e-5 * float(dmu.abs().max()))
+    torch.testing.assert_close(l_.grad, dlam, rtol=0, atol=1e-5 * float(dlam.abs().max()))
+
+
+def test_full_adjoint_sampled_and_invariants():
+    """The full elasticity adjoint workload (bench.py's launch): sampled
+    coefficient gradients and vertex gradients against the oracle, and the
+    translation / Euler / Lame-linearity invariants over the whole mesh."""
+    w = meshgen.elast3d_adjoint(64)
+    m = w.mesh
+    print(f"[full adjoint] {w.name}", flush=True)
+    coords, conn = mesh_to_device(m)
+    mu, lam = vec_to_device(w.mu), vec_to_device(w.lam)
+    dA = vec_to_device(w.dA)
+    dc, dmu, dlam = fei.integrate_adjoint(coords, conn, w.form, dA, mu, lam)
+    A = fei.integrate(coords, conn, w.form, mu, lam)
+    L = float((A.double() * dA.double()).sum())
+    # invariants
+    g = dc.double()
+    X = coords.double()
+    absg = g.abs().sum()
+    assert float(g.sum(dim=1).abs().max()) <= 1e-4 * float(absg)
+    euler = float((X * g).sum())
+    assert abs(euler - L) <= 1e-4 * (float((X * g).abs().sum()) + abs(L))
+    lin = float((mu.double() * dmu.double() + lam.double() * dlam.double()).sum())
+    assert abs(lin - L) <= 1e-5 * float((mu.double() * dmu.double()).abs().sum()
+                                       + (lam.double() * dlam.double()).abs().sum())
+    # sampled coefficient gradients
+    rng = np.random.Generator(np.random.PCG64(9))
+    idx = np.union1d(rng.choice(m.n_elements, 3000, replace=False), m.flattened[:500])
+    gv, gm, gl, _ = oracle.gradient(w.form, m.coords, m.conn[idx], w.dA[idx], w.mu[idx],
+                                    w.lam[idx])
+    dmu_s, dlam_s = dmu.cpu().numpy()[idx], dlam.cpu().numpy()[idx]
+    merr = _coeff_errors(m.coords, m.conn[idx], w.dA[idx], dmu_s, dlam_s, gm, gl)
+    assert merr.max() <= TOL_COEFF
+    # sampled vertex gradients: every element incident to the sampled vertices
+    verts = rng.choice(m.n_vertices, 300, replace=False)
+    inc = np.nonzero(np.isin(m.conn, verts).any(axis=1))[0]
+    gv, _, _, _ = oracle.gradient(w.form, m.coords, m.conn[inc], w.dA[inc], w.mu[inc], w.lam[inc])
+    go = oracle.vertex_gradient(gv, m.conn[inc], m.n_vertices)[verts]
+    sc = vertex_scale(gv, m.conn[inc], m.n_vertices)[verts]
+    gg = dc.cpu().numpy().T[verts]
+    ok = sc > 0
+    assert (np.abs(gg - go).max(axis=1)[ok] / sc[ok]).max() <= TOL_VERTEX

@@ -1,0 +1,207 @@
+"""Forward parity: the HIP path against the FP64 oracle, element by element.
+
+Small cases span several 256-element workgroups and end in a ragged tail; the
+full-size cases use the workloads and launch configuration of bench.py and
+compare a seeded sample of elements (every flattened one included)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+from gpu_util import TOL, element_errors, mesh_to_device, vec_to_device
+
+pytestmark = pytest.mark.gpu
+
+fei = pytest.importorskip("paper_1103_0066_amd")
+
+PRECS = ["fp32", "fp16x2", "bf16x2", "bf16x3"]
+
+
+def _case(name):
+    """Small seeded workloads with the structure of the full ones."""
+    if name == "lap2d_f64":
+        return meshgen.square_mesh(23, 0.2, 11, np.float64), "laplace_p1", None, None
+    if name == "lap2d_f32":
+        return meshgen.square_mesh(23, 0.2, 12, np.float32), "laplace_p1", None, None
+    if name == "lap3d":
+        return meshgen.cube_mesh(6, 5, 5, 0.15, 13), "laplace_p1", None, None
+    if name == "elast3d":
+        m = meshgen.cube_mesh(6, 6, 5, 0.15, 14)
+        m = meshgen.flatten_elements(m, 11, 15)
+        mu, lam = meshgen.lame(m.n_elements, 16)
+        return m, "elastic_p1", mu, lam
+    if name == "elast2d":
+        m = meshgen.square_mesh(20, 0.2, 17, np.float32)
+        mu, lam = meshgen.lame(m.n_elements, 18)
+        return m, "elastic_p1", mu, lam
+    if name == "p2_3d":
+        return meshgen.cube_mesh(5, 5, 5, 0.15, 19), "laplace_p2", None, None
+    if name == "p2_2d":
+        return meshgen.square_mesh(19, 0.2, 20, np.float32), "laplace_p2", None, None
+    raise KeyError(name)
+
+
+CASES = ["lap2d_f64", "lap2d_f32", "lap3d", "elast3d", "elast2d", "p2_3d", "p2_2d"]
+
+
+def _run(mesh, form, mu, lam, precision, **kw):
+    coords, conn = mesh_to_device(mesh)
+    A = fei.integrate(coords, conn, form, vec_to_device(mu), vec_to_device(lam),
+                      precision=precision, **kw)
+    torch.cuda.synchronize()
+    return A.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("case", CASES)
+def test_forward_matches_oracle(case, precision):
+    mesh, form, mu, lam = _case(case)
+    print(f"[forward] {case} {precision} E={mesh.n_elements}", flush=True)
+    A = _run(mesh, form, mu, lam, precision)
+    Ao = oracle.integrate(form, mesh.coords, mesh.conn, mu, lam)
+    err = element_errors(A, Ao)
+    print(f"  max err {err.max():.3e}  p99.9 {np.quantile(err, 0.999):.3e}")
+    assert np.all(np.isfinite(A))
+    assert err.max() <= TOL[precision]
+
+
+def test_forward_is_bitwise_deterministic():
+    mesh, form, mu, lam = _case("elast3d")
+    for prec in PRECS:
+        a = _run(mesh, form, mu, lam, prec)
+        b = _run(mesh, form, mu, lam, prec)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), prec
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_empty_and_single_element(precision):
+    mesh, form, mu, lam = _case("elast3d")
+    coords, conn = mesh_to_device(mesh)
+    A0 = fei.integrate(coords, conn[:0], form, vec_to_device(mu[:0]), vec_to_device(lam[:0]),
+                       precision=precision)
+    assert A0.shape == (0, 12, 12)
+    for e in (0, int(mesh.flattened[0])):
+        one = mesh.conn[e:e + 1]
+        A1 = fei.integrate(coords, torch.from_numpy(one).to(coords.device), form,
+                           vec_to_device(mu[e:e + 1]), vec_to_device(lam[e:e + 1]),
+                           precision=precision).cpu().numpy()
+        Ao = oracle.integrate(form, mesh.coords, one, mu[e:e + 1], lam[e:e + 1])
+        assert element_errors(A1, Ao).max() <= TOL[precision]
+
+
+def _kappa(mesh):
+    X = mesh.coords.astype(np.float64)
+    c = mesh.conn
+    J = np.stack([X[c[:, k]] - X[c[:, 0]] for k in range(1, mesh.dim + 1)], axis=2)
+    B = np.linalg.inv(J)
+    return np.linalg.norm(J, axis=(1, 2)) * np.linalg.norm(B, axis=(1, 2))
+
+
+def test_fp64_path_counters_and_forcing():
+    """tau = 100 flags exactly the flattened tets; tau <= 0 sends every element
+    through FP64; tau = inf none.  Results stay within tolerance in all three."""
+    mesh, form, mu, lam = _case("elast3d")
+    kappa = _kappa(mesh)
+    expect = int(np.sum(kappa > 100.0))
+    assert expect == len(mesh.flattened)
+    Ao = oracle.integrate(form, mesh.coords, mesh.conn, mu, lam)
+    for tau, flagged in ((100.0, expect), (0.0, mesh.n_elements), (-1.0, mesh.n_elements)):
+        cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+        A = _run(mesh, form, mu, lam, "fp32", tau=tau, counters=cnt)
+        assert cnt.cpu().tolist() == [flagged, 0], tau
+        assert element_errors(A, Ao).max() <= TOL["fp32"]
+    cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+    A = _run(mesh, form, mu, lam, "fp32", tau=math.inf, counters=cnt)
+    assert cnt.cpu().tolist() == [0, 0]
+    # without the FP64 path the flattened tets lose accuracy; the rest do not
+    err = element_errors(A, Ao)
+    regular = np.setdiff1d(np.arange(mesh.n_elements), mesh.flattened)
+    assert err[regular].max() <= TOL["fp32"]
+
+
+def test_singular_element_gives_nonfinite_and_is_counted():
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0], [0, 0, 1]], np.float32)
+    conn = np.array([[0, 1, 2, 3], [0, 1, 2, 4]], np.int32)   # coplanar, then regular
+    mesh = meshgen.Mesh(X, conn)
+    for prec in PRECS:
+        cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+        A = _run(mesh, "laplace_p1", None, None, prec, counters=cnt)
+        assert not np.all(np.isfinite(A[0]))
+        assert np.all(np.isfinite(A[1]))
+        assert cnt.cpu().tolist() == [1, 1]
+        Ao = oracle.integrate("laplace_p1", X, conn[1:])
+        assert element_errors(A[1:], Ao).max() <= TOL[prec]
+
+
+def test_validate_mesh_counts_bad_connectivity():
+    mesh, form, mu, lam = _case("lap3d")
+    coords, conn = mesh_to_device(mesh)
+    assert fei.validate_mesh(coords, conn) == 0
+    bad = conn.clone()
+    bad[3, 1] = mesh.n_vertices
+    bad[7, 0] = -2
+    assert fei.validate_mesh(coords, bad) == 2
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads (bench.py's inputs and launch configuration), sampled
+# ---------------------------------------------------------------------------
+
+def _sample(E, flattened, k, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = rng.choice(E, size=min(k, E), replace=False)
+    if flattened is not None and len(flattened):
+        idx = np.union1d(idx, rng.choice(flattened, size=min(2000, len(flattened)), replace=False))
+    idx = np.union1d(idx, [0, E - 1])
+    return np.sort(idx)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_full_elasticity_sampled(precision):
+    w = meshgen.elast3d(64)
+    m = w.mesh
+    print(f"[full] {w.name} {precision}", flush=True)
+    coords, conn = mesh_to_device(m)
+    A = fei.integrate(coords, conn, w.form, vec_to_device(w.mu), vec_to_device(w.lam),
+                      precision=precision)
+    idx = _sample(m.n_elements, m.flattened, 20000, 7)
+    As = A[torch.from_numpy(idx).to(A.device)].cpu().numpy()
+    Ao = oracle.integrate(w.form, m.coords, m.conn[idx], w.mu[idx], w.lam[idx])
+    err = element_errors(As, Ao)
+    print(f"  sampled {len(idx)}: max err {err.max():.3e}  p99.9 {np.quantile(err, 0.999):.3e}")
+    assert err.max() <= TOL[precision]
+    # properties at every element: symmetry and rigid translations in the kernel
+    Af = A.view(m.n_elements, 12, 12)
+    asym = (Af - Af.transpose(1, 2)).abs().amax(dim=(1, 2)) / Af.abs().amax(dim=(1, 2))
+    assert float(asym.max()) <= 2 * TOL[precision]
+    t = torch.zeros(12, 3, device=A.device)
+    for c in range(3):
+        t[c::3, c] = 1.0
+    rows = (Af @ t).abs().amax(dim=(1, 2)) / Af.abs().amax(dim=(1, 2))
+    assert float(rows.max()) <= 20 * TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16x2"])
+def test_full_laplace3d_sampled(precision):
+    w = meshgen.lap3d(64)
+    m = w.mesh
+    coords, conn = mesh_to_device(m)
+    A = fei.integrate(coords, conn, w.form, precision=precision)
+    idx = _sample(m.n_elements, None, 20000, 8)
+    As = A[torch.from_numpy(idx).to(A.device)].cpu().numpy()
+    Ao = oracle.integrate(w.form, m.coords, m.conn[idx])
+    assert element_errors(As, Ao).max() <= TOL[precision]
+    rowsum = A.sum(dim=2).abs().amax(dim=1) / A.abs().amax(dim=(1, 2))
+    assert float(rowsum.max()) <= 10 * TOL[precision]
+
+
+def test_full_laplace2d_every_element():
+    w = meshgen.lap2d(64)
+    m = w.mesh
+    coords, conn = mesh_to_device(m)
+    A = fei.integrate(coords, conn, w.form).cpu().numpy()
+    Ao = oracle.integrate(w.form, m.coords, m.conn)
+    assert element_errors(A, Ao).max() <= TOL["fp32"]
