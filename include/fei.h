@@ -113,7 +113,14 @@ typedef struct fei_options {
     int32_t *counters;      /* optional device int32[2], accumulated (+=):
                                [0] elements that took the FP64 path,
                                [1] elements with det J == 0.  NULL: none. */
-    int32_t tile;           /* elements per workgroup; <= 0 picks the default */
+    int32_t store_rows;     /* how element matrices leave the kernels (a tuning
+                               knob, the paper's interleaved stores, Sec. 4.3):
+                               0 = the tuned default; -1 = every lane stores
+                               its own rows; R > 0 = the wave stages R rows of
+                               all its elements' matrices in LDS and stores
+                               them with contiguous 16-byte pieces (the adjoint
+                               reads dA the same way).  R must divide n with
+                               R*n a multiple of 4; FEI_EUNSUPPORTED otherwise. */
     int32_t reserved[4];    /* must be zero */
 } fei_options;
 
@@ -126,7 +133,7 @@ const char *fei_status_str(int status);
 /* Thread-local message describing the last failing call on this thread. */
 const char *fei_last_error(void);
 
-/* Fills *opt with defaults: FP32, tau = 100, no counters, default tile. */
+/* Fills *opt with defaults: FP32, tau = 100, no counters, tuned staging. */
 int fei_options_default(fei_options *opt);
 
 /* Element matrix size n for (form, dim), or FEI_EINVAL. */

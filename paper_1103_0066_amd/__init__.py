@@ -106,7 +106,8 @@ def _mesh(coords: torch.Tensor, conn: torch.Tensor) -> _lib.FeiMesh:
     return m
 
 
-def _options(precision: str, tau: float, counters: Optional[torch.Tensor]) -> _lib.FeiOptions:
+def _options(precision: str, tau: float, counters: Optional[torch.Tensor],
+             store_rows: int = 0) -> _lib.FeiOptions:
     o = _lib.FeiOptions()
     _lib.check(_lib.load().fei_options_default(ctypes.byref(o)))
     try:
@@ -114,6 +115,7 @@ def _options(precision: str, tau: float, counters: Optional[torch.Tensor]) -> _l
     except KeyError:
         raise ValueError(f"unknown precision {precision!r}") from None
     o.tau = float(tau)
+    o.store_rows = int(store_rows)
     if counters is not None:
         _require(counters, "counters", torch.int32, counters.device, (2,))
         o.counters = counters.data_ptr()
@@ -128,9 +130,10 @@ def integrate(coords: torch.Tensor, conn: torch.Tensor, form: str,
               mu: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None, *,
               precision: str = "fp32", tau: float = 100.0,
               counters: Optional[torch.Tensor] = None,
-              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+              out: Optional[torch.Tensor] = None, store_rows: int = 0) -> torch.Tensor:
     """Element matrices A[e] = G_e : K (no autograd).  ``counters`` (int32[2],
-    device) accumulates [elements on the FP64 path, elements with det J == 0]."""
+    device) accumulates [elements on the FP64 path, elements with det J == 0].
+    ``store_rows`` selects the output staging (fei_options.store_rows)."""
     lib = _lib.load()
     m = _mesh(coords, conn)
     dev = coords.device
@@ -143,7 +146,7 @@ def integrate(coords: torch.Tensor, conn: torch.Tensor, form: str,
         out = torch.empty((E, n, n), dtype=torch.float32, device=dev)
     else:
         _require(out, "out", torch.float32, dev, (E, n, n))
-    o = _options(precision, tau, counters)
+    o = _options(precision, tau, counters, store_rows)
     _lib.check(lib.fei_integrate(ctypes.byref(m), _form_id(form), _ptr(mu), _ptr(lam),
                                  _ptr(out), ctypes.byref(o), _stream(dev)))
     return out
@@ -153,7 +156,8 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
                       mu: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None, *,
                       tau: float = 100.0, dcoords: Optional[torch.Tensor] = None,
                       coeff_grads: bool = True, counters: Optional[torch.Tensor] = None,
-                      dmu: Optional[torch.Tensor] = None, dlam: Optional[torch.Tensor] = None):
+                      dmu: Optional[torch.Tensor] = None, dlam: Optional[torch.Tensor] = None,
+                      store_rows: int = 0):
     """Gradients of L = sum_e <dA_e, A_e>.
 
     Returns (dcoords [dim, N_v] float32, accumulated into ``dcoords`` when given,
@@ -179,7 +183,7 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
         _require(dlam, "dlam", torch.float32, dev, (E,))
     else:
         dmu = dlam = None
-    o = _options("fp32", tau, counters)
+    o = _options("fp32", tau, counters, store_rows)
     _lib.check(lib.fei_integrate_adjoint(
         ctypes.byref(m), _form_id(form), _ptr(mu), _ptr(lam), _ptr(dA),
         dcoords[0].data_ptr(), dcoords[1].data_ptr(),

@@ -35,7 +35,7 @@ class FeiMesh(ctypes.Structure):
 
 class FeiOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tau", ctypes.c_float),
-                ("counters", ctypes.c_void_p), ("tile", ctypes.c_int32),
+                ("counters", ctypes.c_void_p), ("store_rows", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 4)]
 
 

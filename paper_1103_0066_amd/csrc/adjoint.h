@@ -17,17 +17,51 @@
 //   Jbar = sbar s B^T - B^T Bbar B^T        (d|det J| = s J^-T : dJ, dB = -B dJ B)
 //   xbar_{m+1} += Jbar[:, m],  xbar_0 -= sum_m Jbar[:, m]   (FP32 atomics)
 //
-// Flagged elements (quality test) and FP64 coordinates run the geometry
-// reverse in FP64.
+// dA is read through LDS: the wave loads R rows of its 64 elements' dA with
+// consecutive lanes on consecutive 16-byte pieces, then every lane folds its
+// own rows into U.
+//
+// Elements flagged by the quality test run the reverse geometry in FP64, and
+// their U is recomputed in FP64 too: for such a tet (kappa ~ 1e3) the FP32
+// rounding of U alone is amplified to ~1e-4 in dL/dx.  That FP64 fold is done
+// by the whole wave, one lane per unique entry g, from the sparse rows of Kf,
+// so a flagged element costs a few instructions instead of a serial fold.
+// FP64 coordinates run everything in FP64.
 #pragma once
 
 #include "fwd_fma.h"
 
 namespace fei {
 
-template <int FORM, int DIM, typename R>
+template <int FORM, int DIM>
+__device__ KSparse<FORM, DIM> g_ksparse;
+
+// S accessors: from registers (U as accumulated) or from an LDS copy.
+template <int FORM, int DIM, typename AccT>
+struct SRegs {
+    const AccT (&U)[Traits<FORM, DIM>::G];
+    template <typename R>
+    __device__ __forceinline__ R get(int p, int q) const
+    {
+        const R u = R(U[sym_index(Traits<FORM, DIM>::GD, p, q)]);
+        return p == q ? u : R(0.5) * u;
+    }
+};
+
+struct SLds {
+    const double *u;
+    int gd;
+    template <typename R>
+    __device__ __forceinline__ R get(int p, int q) const
+    {
+        const R v = R(u[sym_index(gd, p, q)]);
+        return p == q ? v : R(0.5) * v;
+    }
+};
+
+template <int FORM, int DIM, typename R, typename SAcc>
 __device__ __forceinline__ void adjoint_chain(const R (&adj)[DIM][DIM], R det, float mu_f,
-                                              float lam_f, const float (&U)[Traits<FORM, DIM>::G],
+                                              float lam_f, const SAcc &S,
                                               float (&Jbar)[DIM][DIM], float &mubar,
                                               float &lambar)
 {
@@ -50,10 +84,6 @@ __device__ __forceinline__ void adjoint_chain(const R (&adj)[DIM][DIM], R det, f
             for (int a = 0; a < DIM; ++a) acc += B[m][a] * B[n][a];
             M[m][n] = acc;
         }
-    auto Sv = [&](int p, int q) -> R {
-        const R u = R(U[sym_index(T::GD, p, q)]);
-        return p == q ? u : R(0.5) * u;
-    };
     R sbar;
     R Bbar[DIM][DIM];
     if constexpr (FORM != ELA1) {
@@ -61,7 +91,7 @@ __device__ __forceinline__ void adjoint_chain(const R (&adj)[DIM][DIM], R det, f
 #pragma unroll
         for (int m = 0; m < DIM; ++m)
 #pragma unroll
-            for (int n = 0; n < DIM; ++n) F += Sv(m, n) * M[m][n];
+            for (int n = 0; n < DIM; ++n) F += S.template get<R>(m, n) * M[m][n];
         sbar = c * F;
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
@@ -69,7 +99,7 @@ __device__ __forceinline__ void adjoint_chain(const R (&adj)[DIM][DIM], R det, f
             for (int g = 0; g < DIM; ++g) {
                 R acc = R(0);
 #pragma unroll
-                for (int n = 0; n < DIM; ++n) acc += Sv(k, n) * B[n][g];
+                for (int n = 0; n < DIM; ++n) acc += S.template get<R>(k, n) * B[n][g];
                 Bbar[k][g] = R(2) * c * s * acc;
             }
         mubar = 0.f;
@@ -83,7 +113,7 @@ __device__ __forceinline__ void adjoint_chain(const R (&adj)[DIM][DIM], R det, f
             for (int n = 0; n < DIM; ++n) {
                 R h = R(0);
 #pragma unroll
-                for (int cc = 0; cc < DIM; ++cc) h += Sv(m * DIM + cc, n * DIM + cc);
+                for (int cc = 0; cc < DIM; ++cc) h += S.template get<R>(m * DIM + cc, n * DIM + cc);
                 H[m][n] = h;
             }
 #pragma unroll
@@ -95,8 +125,8 @@ __device__ __forceinline__ void adjoint_chain(const R (&adj)[DIM][DIM], R det, f
                 for (int cc = 0; cc < DIM; ++cc)
 #pragma unroll
                     for (int n = 0; n < DIM; ++n) {
-                        z += Sv(k * DIM + cc, n * DIM + g) * B[n][cc];
-                        y += Sv(k * DIM + g, n * DIM + cc) * B[n][cc];
+                        z += S.template get<R>(k * DIM + cc, n * DIM + g) * B[n][cc];
+                        y += S.template get<R>(k * DIM + g, n * DIM + cc) * B[n][cc];
                     }
                 Z[k][g] = z;
                 Y[k][g] = y;
@@ -144,93 +174,211 @@ __device__ __forceinline__ void adjoint_chain(const R (&adj)[DIM][DIM], R det, f
         }
 }
 
-template <int FORM, int DIM, typename CT>
+// Fold one 4-float piece of dA (entries flat0..flat0+3) into U.
+template <int FORM, int DIM, typename AccT>
+__device__ __forceinline__ void fold_piece(AccT *uacc, int flat0, const float (&r)[4],
+                                           int count)
+{
+    using T = Traits<FORM, DIM>;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= count) break;
+        const int flat = flat0 + k;
+        const int I = flat / T::N, J = flat % T::N;
+        const int a = I / T::NC, cI = I % T::NC, b = J / T::NC, dJ = J % T::NC;
+#pragma unroll
+        for (int mu = 0; mu < DIM; ++mu)
+#pragma unroll
+            for (int nu = 0; nu < DIM; ++nu) {
+                const int g = sym_index(T::GD, mu * T::NC + cI, nu * T::NC + dJ);
+                uacc[g] += AccT(kval<FORM, DIM>(a, b, mu, nu)) * AccT(r[k]);
+            }
+    }
+}
+
+// Vertex scatter.  The wave's 64 elements reference (DIM+1)*64 vertices but,
+// on any mesh with locality, far fewer distinct ones (~48 for consecutive Kuhn
+// tets).  The wave first merges its contributions per vertex in an LDS
+// open-addressing table (CAS on the key, LDS float atomics on the values),
+// then issues one global FP32 atomic per distinct vertex and component.
+constexpr int kHashSlots = 512;   // >= 2 x the wave's 256 vertex references
+
+__device__ __forceinline__ int hash_slot(int v)
+{
+    return int((unsigned(v) * 2654435761u) >> (32 - 9));  // Knuth multiplicative, 9 bits
+}
+
+template <int DIM>
+__device__ __forceinline__ void scatter_vertices(const AdjParams &p, const int (&v)[DIM + 1],
+                                                 const float (&Jbar)[DIM][DIM], bool valid,
+                                                 int *key, float *val, int lane)
+{
+    for (int i = lane; i < kHashSlots; i += 64) {
+        key[i] = -1;
+#pragma unroll
+        for (int al = 0; al < DIM; ++al) val[i * DIM + al] = 0.f;
+    }
+    wave_sync();
+    if (valid) {
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a) {
+            // contribution to vertex a: column a-1 of Jbar, or minus the row sums
+            float c[DIM];
+#pragma unroll
+            for (int al = 0; al < DIM; ++al) {
+                if (a > 0) {
+                    c[al] = Jbar[al][a - 1];
+                } else {
+                    float s0 = 0.f;
+#pragma unroll
+                    for (int m = 0; m < DIM; ++m) s0 += Jbar[al][m];
+                    c[al] = -s0;
+                }
+            }
+            int h = hash_slot(v[a]);
+            for (int probe = 0; probe < kHashSlots; ++probe) {
+                const int old = atomicCAS(key + h, -1, v[a]);
+                if (old == -1 || old == v[a]) break;
+                h = (h + 1) & (kHashSlots - 1);
+            }
+#pragma unroll
+            for (int al = 0; al < DIM; ++al) atomicAdd(val + h * DIM + al, c[al]);
+        }
+    }
+    wave_sync();
+    float *X[3] = {p.dx, p.dy, p.dz};
+    for (int i = lane; i < kHashSlots; i += 64) {
+        const int k = key[i];
+        if (k >= 0) {
+#pragma unroll
+            for (int al = 0; al < DIM; ++al) unsafeAtomicAdd(X[al] + k, val[i * DIM + al]);
+        }
+    }
+}
+
+template <int FORM, int DIM, typename CT, int R>
 __global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p)
 {
     using T = Traits<FORM, DIM>;
-    constexpr int N = T::N;
-    constexpr int VEC = (N % 4 == 0) ? 4 : (N % 2 == 0) ? 2 : 1;
-    using V = typename VecT<VEC>::type;
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t e = blk * 256 + threadIdx.x;
-    if (e >= p.m.n_elements) return;
-    int v[DIM + 1];
-    load_conn<DIM>(p.m.conn, e, v);
-    CT xv[DIM + 1][DIM];
-    gather<DIM>(p.m, v, xv);
-    float mu = 0.f, lam = 0.f;
-    if constexpr (FORM == ELA1) {
-        mu = __builtin_nontemporal_load(p.mu + e);
-        lam = __builtin_nontemporal_load(p.lam + e);
-    }
+    using S = Stage<FORM, DIM, R>;
+    using AccT = typename std::conditional<sizeof(CT) == 8, double, float>::type;
+    constexpr int NN = S::NN;
+    constexpr int GP = ((T::G + 1) / 2) * 2;
+    constexpr int SW = (R > 0) ? ((64 * S::STR > NN) ? 64 * S::STR : NN) : ((NN + 3) / 4) * 4;
+    __shared__ __attribute__((aligned(16))) float s_stage[4][SW];
+    __shared__ double s_u64[4][GP];
+    __shared__ int s_key[4][kHashSlots];
+    __shared__ float s_val[4][kHashSlots * DIM];
 
-    // U = Kf applied to dA (streamed row by row)
-    float U[T::G];
-#pragma unroll
-    for (int g = 0; g < T::G; ++g) U[g] = 0.f;
-    const float *__restrict__ dAe = p.dA + e * (int64_t)(N * N);
-#pragma unroll
-    for (int I = 0; I < N; ++I) {
-#pragma unroll
-        for (int J0 = 0; J0 < N; J0 += VEC) {
-            const V w = __builtin_nontemporal_load(reinterpret_cast<const V *>(dAe + I * N + J0));
-            float r[VEC];
-            __builtin_memcpy(r, &w, sizeof(V));
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) {
-                const int J = J0 + k;
-                const int a = I / T::NC, cI = I % T::NC, b = J / T::NC, dJ = J % T::NC;
-#pragma unroll
-                for (int mu_ = 0; mu_ < DIM; ++mu_)
-#pragma unroll
-                    for (int nu = 0; nu < DIM; ++nu) {
-                        const int g = sym_index(T::GD, mu_ * T::NC + cI, nu * T::NC + dJ);
-                        U[g] = fmaf(kval<FORM, DIM>(a, b, mu_, nu), r[k], U[g]);
-                    }
-            }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t E = p.m.n_elements;
+    const int64_t e0 = blk * 256 + wave * 64;
+    const int64_t e = e0 + lane;
+    const bool valid = e < E;
+    float *st = s_stage[wave];
+
+    int v[DIM + 1] = {};
+    CT xv[DIM + 1][DIM] = {};
+    float mu = 0.f, lam = 0.f;
+    if (valid) {
+        load_conn<DIM>(p.m.conn, e, v);
+        gather<DIM>(p.m, v, xv);
+        if constexpr (FORM == ELA1) {
+            mu = __builtin_nontemporal_load(p.mu + e);
+            lam = __builtin_nontemporal_load(p.lam + e);
         }
     }
 
-    float Jbar[DIM][DIM], mubar, lambar;
+    // U = folded K^T applied to dA
+    AccT U[T::G];
+#pragma unroll
+    for (int g = 0; g < T::G; ++g) U[g] = AccT(0);
+    if constexpr (R > 0) {
+#pragma unroll
+        for (int c = 0; c < S::NCHUNK; ++c) {
+#pragma unroll
+            for (int k = 0; k < S::NV4; ++k) {
+                const int f = lane + 64 * k;
+                const int el = f / S::NV4, part = f - el * S::NV4;
+                f32x4_t r = {0.f, 0.f, 0.f, 0.f};
+                if (e0 + el < E)
+                    r = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(
+                        p.dA + (e0 + el) * (int64_t)NN + c * S::CH + 4 * part));
+                *reinterpret_cast<f32x4_t *>(st + el * S::STR + 4 * part) = r;
+            }
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < S::CH; k += 4) {
+                const f32x4_t w = *reinterpret_cast<const f32x4_t *>(st + lane * S::STR + k);
+                const float r[4] = {w[0], w[1], w[2], w[3]};
+                fold_piece<FORM, DIM, AccT>(U, c * S::CH + k, r, 4);
+            }
+            wave_sync();
+        }
+    } else if (valid) {
+        const float *__restrict__ dAe = p.dA + e * (int64_t)NN;
+#pragma unroll
+        for (int k = 0; k < NN; k += 4) {
+            float r[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (k + i < NN) r[i] = __builtin_nontemporal_load(dAe + k + i);
+            fold_piece<FORM, DIM, AccT>(U, k, r, NN - k < 4 ? NN - k : 4);
+        }
+    }
+
+    float Jbar[DIM][DIM], mubar = 0.f, lambar = 0.f;
     bool flag = false, singular = false;
     if constexpr (sizeof(CT) == 8) {
         double J[DIM][DIM], adj[DIM][DIM];
         jacobian<DIM>(xv, J);
         const double det = adjugate(J, adj);
-        singular = (det == 0.0);
-        adjoint_chain<FORM, DIM>(adj, det, mu, lam, U, Jbar, mubar, lambar);
+        singular = valid && det == 0.0;
+        adjoint_chain<FORM, DIM>(adj, det, mu, lam, SRegs<FORM, DIM, AccT>{U}, Jbar, mubar, lambar);
     } else {
         float J[DIM][DIM], adj[DIM][DIM];
         jacobian<DIM>(xv, J);
         const float det = adjugate(J, adj);
-        flag = needs_fp64<DIM>(J, adj, det, p.tau2);
-        if (!flag) {
-            adjoint_chain<FORM, DIM>(adj, det, mu, lam, U, Jbar, mubar, lambar);
-        } else {
-            double Jd[DIM][DIM], adjd[DIM][DIM];
-            jacobian<DIM>(xv, Jd);
-            const double detd = adjugate(Jd, adjd);
-            singular = (detd == 0.0);
-            adjoint_chain<FORM, DIM>(adjd, detd, mu, lam, U, Jbar, mubar, lambar);
+        flag = valid && needs_fp64<DIM>(J, adj, det, p.tau2);
+        if (!flag)
+            adjoint_chain<FORM, DIM>(adj, det, mu, lam, SRegs<FORM, DIM, AccT>{U}, Jbar, mubar,
+                                     lambar);
+        // flagged elements, one at a time: FP64 fold by the wave, FP64 chain by the owner
+        unsigned long long fm = __ballot(flag);
+        while (fm) {
+            const int L = __ffsll(fm) - 1;
+            fm &= fm - 1;
+            const int64_t eL = e0 + L;
+            for (int k = lane; k < NN; k += 64)
+                st[k] = __builtin_nontemporal_load(p.dA + eL * (int64_t)NN + k);
+            wave_sync();
+            if (lane < T::G) {
+                constexpr int NZ = KSparseShape<FORM, DIM>::NNZ;
+                const KSparse<FORM, DIM> &ks = g_ksparse<FORM, DIM>;
+                double u = 0.0;
+                for (int t = 0; t < NZ; ++t)
+                    u += double(ks.coef[lane][t]) * double(st[ks.ij[lane][t]]);
+                s_u64[wave][lane] = u;
+            }
+            wave_sync();
+            if (lane == L) {
+                double Jd[DIM][DIM], adjd[DIM][DIM];
+                jacobian<DIM>(xv, Jd);
+                const double detd = adjugate(Jd, adjd);
+                singular = (detd == 0.0);
+                adjoint_chain<FORM, DIM>(adjd, detd, mu, lam, SLds{s_u64[wave], T::GD}, Jbar,
+                                         mubar, lambar);
+            }
+            wave_sync();
         }
     }
     count_flags(p.counters, flag, singular);
-
-    float *X[3] = {p.dx, p.dy, p.dz};
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        float s0 = 0.f;
-#pragma unroll
-        for (int m = 0; m < DIM; ++m) {
-            unsafeAtomicAdd(X[a] + v[m + 1], Jbar[a][m]);
-            s0 += Jbar[a][m];
-        }
-        unsafeAtomicAdd(X[a] + v[0], -s0);
-    }
     if constexpr (FORM == ELA1) {
-        if (p.dmu) p.dmu[e] = mubar;
-        if (p.dlam) p.dlam[e] = lambar;
+        if (valid && p.dmu) p.dmu[e] = mubar;
+        if (valid && p.dlam) p.dlam[e] = lambar;
     }
+    scatter_vertices<DIM>(p, v, Jbar, valid, s_key[wave], s_val[wave], lane);
 }
 
 }  // namespace fei

@@ -55,7 +55,7 @@ fei_options defaults()
     o.precision = FEI_PREC_FP32;
     o.tau = 100.0f;
     o.counters = nullptr;
-    o.tile = 0;
+    o.store_rows = 0;
     return o;
 }
 
@@ -226,7 +226,7 @@ int fei_integrate(const fei_mesh *m, int form, const float *mu, const float *lam
     if (m->n_elements == 0) return FEI_OK;
     if (!A) return fail(FEI_EINVAL, "A is NULL");
     if (!aligned(A, 16)) return fail(FEI_EINVAL, "A must be 16-byte aligned");
-    const Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision};
+    const Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision, o.store_rows};
     FwdLauncher launch = find_forward(v);
     if (!launch) return fail(FEI_EUNSUPPORTED, "no forward kernel for this variant");
     FwdParams p;
@@ -261,7 +261,7 @@ int fei_integrate_adjoint(const fei_mesh *m, int form, const float *mu, const fl
     if (!dx || !dy || (m->dim == 3 && !dz)) return fail(FEI_EINVAL, "dx/dy/dz missing");
     if (!aligned(dx, 4) || !aligned(dy, 4) || (dz && !aligned(dz, 4)))
         return fail(FEI_EINVAL, "dx/dy/dz misaligned");
-    const Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision};
+    const Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision, o.store_rows};
     AdjLauncher launch = find_adjoint(v);
     if (!launch) return fail(FEI_EUNSUPPORTED, "no adjoint kernel for this variant");
     AdjParams p;

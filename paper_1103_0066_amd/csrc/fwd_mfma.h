@@ -20,8 +20,7 @@
 // as one 16-byte vector (64 contiguous bytes per element per M tile).
 #pragma once
 
-#include "geometry.h"
-#include "shapes.h"
+#include "fwd_fma.h"
 
 namespace fei {
 
@@ -98,27 +97,42 @@ __device__ __forceinline__ int split_gf(const float (&Gf)[Traits<FORM, DIM>::G],
     return E;
 }
 
-template <int FORM, int DIM, typename CT, int PREC>
+// LDS layout of the MFMA kernel: per wave, the split-Gf rows of its 64
+// elements (B operand source), later reused to stage 16 elements' matrices.
+template <int FORM, int DIM, int PREC>
+struct MfmaLds {
+    using S = MfmaShape<FORM, DIM, PREC>;
+    static constexpr bool STAGED = (S::NN % 4 == 0);
+    static constexpr int OSTR = S::NN + 4;                    // staged row stride (floats)
+    static constexpr int BBYTES = 64 * S::BROW * 2;           // split-Gf rows of a wave
+    static constexpr int OBYTES = STAGED ? 16 * OSTR * 4 : 0;  // 16 staged matrices
+    static constexpr int WBYTES = ((BBYTES > OBYTES ? BBYTES : OBYTES) + 15) / 16 * 16;
+};
+
+template <int FORM, int DIM, typename CT, int PREC, bool DIRECT>
 __global__ __launch_bounds__(256) void fwd_mfma_kernel(FwdParams p)
 {
     using T = Traits<FORM, DIM>;
     using S = MfmaShape<FORM, DIM, PREC>;
+    using L = MfmaLds<FORM, DIM, PREC>;
     __shared__ uint4 s_frag[S::NFRAG];
-    __shared__ __attribute__((aligned(16))) uint16_t s_b[256 * S::BROW];
+    __shared__ __attribute__((aligned(16))) unsigned char s_wave[4][L::WBYTES];
     __shared__ int s_exp[256];
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    uint16_t *s_b = reinterpret_cast<uint16_t *>(s_wave[wave]);
     // stage the K fragments (read-only, L2-resident table)
     const uint4 *gfr = reinterpret_cast<const uint4 *>(g_frags<FORM, DIM, PREC>.v);
     for (int i = tid; i < S::NFRAG; i += 256) s_frag[i] = gfr[i];
 
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t e0 = blk * 256;
+    const int64_t e0 = blk * 256 + wave * 64;
     const int64_t E = p.m.n_elements;
 
     // phase 1: geometry, one lane per element
     {
-        const int64_t e = e0 + tid;
+        const int64_t e = e0 + lane;
         float Gf[T::G];
         bool flag = false, singular = false;
         if (e < E) {
@@ -137,53 +151,89 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(FwdParams p)
             for (int g = 0; g < T::G; ++g) Gf[g] = 0.f;
         }
         count_flags(p.counters, flag, singular);
-        s_exp[tid] = split_gf<FORM, DIM, PREC>(Gf, s_b + tid * S::BROW);
+        s_exp[tid] = split_gf<FORM, DIM, PREC>(Gf, s_b + lane * S::BROW);
     }
     __syncthreads();
 
-    // phase 2: MFMA over the wave's 64 elements (4 column groups of 16)
-    const int lane = tid & 63, wave = tid >> 6;
+    // phase 2: the wave's 64 elements as 4 MFMA column groups of 16
     const int n = lane & 15, q = lane >> 4;
     uint4 bf[4][S::KS];
     int ex[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        const int el = wave * 64 + g * 16 + n;
+        const int el = g * 16 + n;
 #pragma unroll
         for (int s = 0; s < S::KS; ++s)
             bf[g][s] = *reinterpret_cast<const uint4 *>(s_b + el * S::BROW + 32 * s + 8 * q);
-        ex[g] = s_exp[el];
+        ex[g] = s_exp[wave * 64 + el];
     }
+    if constexpr (DIRECT || !L::STAGED) {
+        // each lane stores its 4 consecutive entries of one element per M tile
 #pragma unroll
-    for (int t = 0; t < S::MT; ++t) {
-        floatx4_t acc[4];
+        for (int t = 0; t < S::MT; ++t) {
+            floatx4_t acc[4];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) acc[g] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+            for (int g = 0; g < 4; ++g) acc[g] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < S::KS; ++s) {
-            const uint4 a = s_frag[(t * S::KS + s) * 64 + lane];
+            for (int s = 0; s < S::KS; ++s) {
+                const uint4 a = s_frag[(t * S::KS + s) * 64 + lane];
 #pragma unroll
-            for (int g = 0; g < 4; ++g) acc[g] = mfma_step<PREC>(a, bf[g][s], acc[g]);
+                for (int g = 0; g < 4; ++g) acc[g] = mfma_step<PREC>(a, bf[g][s], acc[g]);
+            }
+            const int m0 = 16 * t + 4 * q;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int64_t e = e0 + g * 16 + n;
+                if (e >= E) continue;
+                floatx4_t r = acc[g];
+                if constexpr (PREC == P_FP16X2) {
+                    r[0] = ldexpf(r[0], ex[g]); r[1] = ldexpf(r[1], ex[g]);
+                    r[2] = ldexpf(r[2], ex[g]); r[3] = ldexpf(r[3], ex[g]);
+                }
+                float *Ae = p.A + e * (int64_t)S::NN;
+                if constexpr (S::NN % 4 == 0) {
+                    if (m0 < S::NN)
+                        *reinterpret_cast<float4 *>(Ae + m0) = make_float4(r[0], r[1], r[2], r[3]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (m0 + i < S::NN) Ae[m0 + i] = r[i];
+                }
+            }
         }
-        const int m0 = 16 * t + 4 * q;  // first of the lane's 4 entries
+    } else {
+        // per column group: all M tiles into LDS, then contiguous 16-byte stores
+        float *so = reinterpret_cast<float *>(s_wave[wave]);
+        wave_sync();  // the B fragments above have been read from this region
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const int64_t e = e0 + wave * 64 + g * 16 + n;
-            if (e >= E) continue;
-            floatx4_t r = acc[g];
-            if constexpr (PREC == P_FP16X2) {
-                r[0] = ldexpf(r[0], ex[g]); r[1] = ldexpf(r[1], ex[g]);
-                r[2] = ldexpf(r[2], ex[g]); r[3] = ldexpf(r[3], ex[g]);
-            }
-            float *Ae = p.A + e * (int64_t)S::NN;
-            if constexpr (S::NN % 4 == 0) {
-                if (m0 < S::NN)
-                    *reinterpret_cast<float4 *>(Ae + m0) = make_float4(r[0], r[1], r[2], r[3]);
-            } else {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (m0 + i < S::NN) Ae[m0 + i] = r[i];
+            for (int t = 0; t < S::MT; ++t) {
+                floatx4_t acc = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < S::KS; ++s)
+                    acc = mfma_step<PREC>(s_frag[(t * S::KS + s) * 64 + lane], bf[g][s], acc);
+                const int m0 = 16 * t + 4 * q;
+                if constexpr (PREC == P_FP16X2) {
+                    acc[0] = ldexpf(acc[0], ex[g]); acc[1] = ldexpf(acc[1], ex[g]);
+                    acc[2] = ldexpf(acc[2], ex[g]); acc[3] = ldexpf(acc[3], ex[g]);
+                }
+                if (m0 < S::NN)
+                    *reinterpret_cast<floatx4_t *>(so + n * L::OSTR + m0) = acc;
             }
+            wave_sync();
+            constexpr int NV4 = S::NN / 4;      // 16-byte pieces per element
+            const int64_t eg = e0 + g * 16;
+            float *dst = p.A + eg * (int64_t)S::NN;
+#pragma unroll
+            for (int k = 0; k < (16 * NV4 + 63) / 64; ++k) {
+                const int f = lane + 64 * k;
+                if (f >= 16 * NV4) break;
+                const int el = f / NV4, part = f - el * NV4;
+                const floatx4_t r = *reinterpret_cast<const floatx4_t *>(so + el * L::OSTR + 4 * part);
+                if (eg + el < E) *reinterpret_cast<floatx4_t *>(dst + 4 * f) = r;
+            }
+            wave_sync();
         }
     }
 }

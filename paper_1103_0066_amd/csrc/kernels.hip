@@ -1,6 +1,8 @@
 // All device code of libfei: kernel instantiations and the launcher tables
 // the host layer dispatches through.  One translation unit, so the
 // __constant__ reference tables exist once per device module.
+#include <type_traits>
+
 #include "adjoint.h"
 #include "fwd_fma.h"
 #include "fwd_mfma.h"
@@ -16,38 +18,120 @@ constexpr int kBlock = 256;
 
 inline unsigned grid_for(int64_t E) { return unsigned((E + kBlock - 1) / kBlock); }
 
-template <int F, int D, typename CT>
+template <int F, int D, typename CT, int R>
 hipError_t launch_fwd_fma(const FwdParams &p, hipStream_t s)
 {
-    hipLaunchKernelGGL((fwd_fma_kernel<F, D, CT>), dim3(grid_for(p.m.n_elements)), dim3(kBlock),
-                       0, s, p);
-    return hipGetLastError();
-}
-
-template <int F, int D, typename CT, int PREC>
-hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
-{
-    hipLaunchKernelGGL((fwd_mfma_kernel<F, D, CT, PREC>), dim3(grid_for(p.m.n_elements)),
+    hipLaunchKernelGGL((fwd_fma_kernel<F, D, CT, R>), dim3(grid_for(p.m.n_elements)),
                        dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 
-template <int F, int D, typename CT>
-hipError_t launch_adj_fma(const AdjParams &p, hipStream_t s)
+template <int F, int D, typename CT, int PREC, bool DIRECT>
+hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
 {
-    hipLaunchKernelGGL((adj_fma_kernel<F, D, CT>), dim3(grid_for(p.m.n_elements)), dim3(kBlock),
-                       0, s, p);
+    hipLaunchKernelGGL((fwd_mfma_kernel<F, D, CT, PREC, DIRECT>), dim3(grid_for(p.m.n_elements)),
+                       dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 
-template <int F, int D, typename CT>
-FwdLauncher fwd_for_prec(int prec)
+template <int F, int D, typename CT, int R>
+hipError_t launch_adj_fma(const AdjParams &p, hipStream_t s)
 {
-    switch (prec) {
-    case P_FP32: return &launch_fwd_fma<F, D, CT>;
-    case P_FP16X2: return &launch_fwd_mfma<F, D, CT, P_FP16X2>;
-    case P_BF16X2: return &launch_fwd_mfma<F, D, CT, P_BF16X2>;
-    case P_BF16X3: return &launch_fwd_mfma<F, D, CT, P_BF16X3>;
+    hipLaunchKernelGGL((adj_fma_kernel<F, D, CT, R>), dim3(grid_for(p.m.n_elements)),
+                       dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+// Staging rows R that fit: R divides n, R*n floats is a whole number of
+// 16-byte pieces, and four waves' staging buffers fit in the 160 KB LDS.
+template <int F, int D, int R>
+constexpr bool rows_ok()
+{
+    constexpr int N = Traits<F, D>::N;
+    return R == 0 || (N % R == 0 && (R * N) % 4 == 0 && 4 * 64 * (R * N + 4) * 4 <= 160 * 1024);
+}
+
+// Tuned defaults of the staging rows.  Forward: whole matrices (measured
+// fastest for every form on MI355X); adjoint: a third of them or less, which
+// leaves LDS room for the vertex-merge table.
+template <int F, int D>
+constexpr int default_rows()
+{
+    constexpr int N = Traits<F, D>::N;
+    return (N * N) % 4 == 0 && N % 4 != 3 ? N : 0;
+}
+
+template <int F, int D>
+constexpr int default_adj_rows()
+{
+    constexpr int N = Traits<F, D>::N;
+    if constexpr (N == 12) return 3;
+    else if constexpr (N == 4) return 4;
+    else if constexpr (N == 10 || N == 6) return 2;
+    else return 0;
+}
+
+template <int F, int D, typename CT, int R>
+FwdLauncher fwd_fma_if_ok()
+{
+    if constexpr (rows_ok<F, D, R>()) return &launch_fwd_fma<F, D, CT, R>;
+    else return nullptr;
+}
+
+template <int F, int D, typename CT, int R>
+AdjLauncher adj_fma_if_ok()
+{
+    if constexpr (rows_ok<F, D, R>()) return &launch_adj_fma<F, D, CT, R>;
+    else return nullptr;
+}
+
+inline int resolve_rows(int rows, int def) { return rows == 0 ? def : (rows < 0 ? 0 : rows); }
+
+template <int F, int D, typename CT>
+FwdLauncher fwd_fma_rows(int rows)
+{
+    switch (resolve_rows(rows, default_rows<F, D>())) {
+    case 0: return fwd_fma_if_ok<F, D, CT, 0>();
+    case 2: return fwd_fma_if_ok<F, D, CT, 2>();
+    case 3: return fwd_fma_if_ok<F, D, CT, 3>();
+    case 4: return fwd_fma_if_ok<F, D, CT, 4>();
+    case 6: return fwd_fma_if_ok<F, D, CT, 6>();
+    case 10: return fwd_fma_if_ok<F, D, CT, 10>();
+    case 12: return fwd_fma_if_ok<F, D, CT, 12>();
+    default: return nullptr;
+    }
+}
+
+template <int F, int D, typename CT>
+AdjLauncher adj_fma_rows(int rows)
+{
+    switch (resolve_rows(rows, default_adj_rows<F, D>())) {
+    case 0: return adj_fma_if_ok<F, D, CT, 0>();
+    case 2: return adj_fma_if_ok<F, D, CT, 2>();
+    case 3: return adj_fma_if_ok<F, D, CT, 3>();
+    case 4: return adj_fma_if_ok<F, D, CT, 4>();
+    case 6: return adj_fma_if_ok<F, D, CT, 6>();
+    default: return nullptr;
+    }
+}
+
+template <int F, int D, typename CT>
+FwdLauncher fwd_for_prec(const Variant &v)
+{
+    if (v.precision == P_FP32) return fwd_fma_rows<F, D, CT>(v.rows);
+    // MFMA form: staged stores of whole matrices (0, or rows = n), or direct (-1)
+    const bool direct = v.rows < 0;
+    if (v.rows > 0 && v.rows != Traits<F, D>::N) return nullptr;
+    switch (v.precision) {
+    case P_FP16X2:
+        return direct ? &launch_fwd_mfma<F, D, CT, P_FP16X2, true>
+                      : &launch_fwd_mfma<F, D, CT, P_FP16X2, false>;
+    case P_BF16X2:
+        return direct ? &launch_fwd_mfma<F, D, CT, P_BF16X2, true>
+                      : &launch_fwd_mfma<F, D, CT, P_BF16X2, false>;
+    case P_BF16X3:
+        return direct ? &launch_fwd_mfma<F, D, CT, P_BF16X3, true>
+                      : &launch_fwd_mfma<F, D, CT, P_BF16X3, false>;
     default: return nullptr;
     }
 }
@@ -55,15 +139,14 @@ FwdLauncher fwd_for_prec(int prec)
 template <int F, int D>
 FwdLauncher fwd_for_coords(const Variant &v)
 {
-    return v.coord_f64 ? fwd_for_prec<F, D, double>(v.precision)
-                       : fwd_for_prec<F, D, float>(v.precision);
+    return v.coord_f64 ? fwd_for_prec<F, D, double>(v) : fwd_for_prec<F, D, float>(v);
 }
 
 template <int F, int D>
 AdjLauncher adj_for_coords(const Variant &v)
 {
     if (v.precision != P_FP32) return nullptr;
-    return v.coord_f64 ? &launch_adj_fma<F, D, double> : &launch_adj_fma<F, D, float>;
+    return v.coord_f64 ? adj_fma_rows<F, D, double>(v.rows) : adj_fma_rows<F, D, float>(v.rows);
 }
 
 __global__ void validate_kernel(MeshView m, int nv_per, unsigned long long *n_bad)

@@ -39,6 +39,7 @@ struct Variant {
     int dim;        // 2 or 3
     int coord_f64;  // 0/1
     int precision;  // fei_precision
+    int rows;       // fei_options.store_rows: 0 default, -1 direct, R > 0 staged
 };
 
 using FwdLauncher = hipError_t (*)(const FwdParams &, hipStream_t);

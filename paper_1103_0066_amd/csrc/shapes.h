@@ -37,6 +37,21 @@ struct FragTable {
     uint16_t v[MfmaShape<FORM, DIM, PREC>::NFRAG * 8];
 };
 
+// Sparse rows of the folded tensor: for every unique pair g the nonzero
+// entries (flat element-matrix index, integer coefficient), padded with
+// zero coefficients to NNZ.  U_g = sum_t coef[g][t] * dA[ij[g][t]] is the
+// folded K^T applied to dA.
+template <int FORM, int DIM>
+struct KSparseShape {
+    static constexpr int NNZ = (FORM == LAP2) ? ((DIM == 3) ? 72 : 32) : 8;
+};
+
+template <int FORM, int DIM>
+struct KSparse {
+    int16_t ij[Traits<FORM, DIM>::G][KSparseShape<FORM, DIM>::NNZ];
+    float coef[Traits<FORM, DIM>::G][KSparseShape<FORM, DIM>::NNZ];
+};
+
 FEI_HD constexpr void sym_pair(int gd, int gamma, int &p, int &q)
 {
     for (int i = 0; i < gd; ++i)

@@ -80,6 +80,31 @@ def test_adjoint_matches_oracle(case):
     _check_against_oracle(mesh, form, mu, lam, dA)
 
 
+@pytest.mark.parametrize("case,rows", [("elast3d", r) for r in (-1, 2, 3, 4, 6)] +
+                         [("lap3d", r) for r in (-1, 2, 4)] + [("p2_3d", r) for r in (-1, 2)] +
+                         [("elast2d", r) for r in (-1, 2, 6)])
+def test_adjoint_staging_modes(case, rows):
+    mesh, form, mu, lam = _case(case)
+    n = fei.local_size(form, mesh.dim)
+    dA = meshgen.upstream(mesh.n_elements, n, 52)
+    coords, conn = mesh_to_device(mesh)
+    outs = []
+    for r in (rows, 0):
+        dc, dmu, dlam = fei.integrate_adjoint(coords, conn, form, vec_to_device(dA),
+                                              vec_to_device(mu), vec_to_device(lam),
+                                              store_rows=r)
+        outs.append((dc.cpu().numpy().T.astype(np.float64),
+                     None if dmu is None else dmu.cpu().numpy()))
+    gv, gm, gl, _ = oracle.gradient(form, mesh.coords, mesh.conn, dA, mu, lam)
+    go = oracle.vertex_gradient(gv, mesh.conn, mesh.n_vertices)
+    scale = vertex_scale(gv, mesh.conn, mesh.n_vertices)
+    used = scale > 0
+    for g, dmu in outs:
+        assert (np.abs(g - go).max(axis=1)[used] / scale[used]).max() <= TOL_VERTEX
+    if outs[0][1] is not None:   # per-element outputs need no atomics: identical bits
+        assert np.array_equal(outs[0][1].view(np.uint32), outs[1][1].view(np.uint32))
+
+
 @pytest.mark.parametrize("flat", [False, True])
 def test_adjoint_fd_submesh(flat):
     """The 48-tet sub-mesh: GPU vs the oracle gradient and FP64 central differences."""

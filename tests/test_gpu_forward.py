@@ -68,6 +68,37 @@ def test_forward_matches_oracle(case, precision):
     assert err.max() <= TOL[precision]
 
 
+# every output staging mode of each form (fei_options.store_rows)
+STAGING = [("elast3d", "fp32", r) for r in (-1, 2, 3, 4, 6, 12)] + \
+          [("lap3d", "fp32", r) for r in (-1, 2, 4)] + \
+          [("p2_3d", "fp32", r) for r in (-1, 2, 10)] + \
+          [("elast2d", "fp32", r) for r in (-1, 2, 6)] + \
+          [("p2_2d", "fp32", r) for r in (-1, 2, 6)] + \
+          [("lap2d_f64", "fp32", -1)] + \
+          [(c, pr, r) for c, n in (("elast3d", 12), ("lap3d", 4), ("p2_3d", 10), ("elast2d", 6))
+           for pr in ("fp16x2", "bf16x3") for r in (-1, n)]
+
+
+@pytest.mark.parametrize("case,precision,rows", STAGING)
+def test_forward_staging_modes(case, precision, rows):
+    mesh, form, mu, lam = _case(case)
+    A = _run(mesh, form, mu, lam, precision, store_rows=rows)
+    Ao = oracle.integrate(form, mesh.coords, mesh.conn, mu, lam)
+    assert element_errors(A, Ao).max() <= TOL[precision]
+    # identical to the default mode bit for bit (same arithmetic, other stores)
+    A0 = _run(mesh, form, mu, lam, precision)
+    assert np.array_equal(A.view(np.uint32), A0.view(np.uint32))
+
+
+def test_unsupported_staging_is_rejected():
+    mesh, form, mu, lam = _case("elast3d")
+    coords, conn = mesh_to_device(mesh)
+    for prec, rows in (("fp32", 5), ("fp32", 1), ("fp16x2", 3)):
+        with pytest.raises(fei.FeiError):
+            fei.integrate(coords, conn, form, vec_to_device(mu), vec_to_device(lam),
+                          precision=prec, store_rows=rows)
+
+
 def test_forward_is_bitwise_deterministic():
     mesh, form, mu, lam = _case("elast3d")
     for prec in PRECS:
