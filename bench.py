@@ -30,6 +30,39 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 METRIC = "element matrices/s + achieved GB/s, 3D P1 elasticity, plain FP32 vs MFMA form"
 
 
+def kernel_source_digest() -> str:
+    """Digest of the device sources; a stored traffic figure is only valid for it."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1103_0066_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel_tag: str):
+    """HBM bytes per launch from profiles/traffic_<tag>.txt (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy of known size), or None if absent or
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse_args():
     p = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     p.add_argument("--gpus", type=int, default=1)
@@ -38,6 +71,8 @@ def parse_args():
     p.add_argument("--n", type=int, default=64, help="cells per side of the cube")
     p.add_argument("--legs", default="all", help="'all' or 'fp32' (headline only)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-ref", action="store_true",
+                   help="also run a plain 512 MiB device copy (reference for PMC byte counters)")
     return p.parse_args()
 
 
@@ -142,9 +177,11 @@ def main():
                    "vertices": Nv, "precision": "fp32", "tau": 100.0,
                    "algorithmic_bytes_per_step": fwd_bytes},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "fwd_fma_kernel<elastic_p1, 3, float>",
-                     "kernel_ms_mean": head["kernel_ms_mean"]},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic("elastic_p1_3d_fwd_fp32"),
+                     "kernel": "fwd_fma_kernel<elastic_p1, 3, float, 12>",
+                     "kernel_ms_mean": head["kernel_ms_mean"],
+                     "algorithmic_bytes_per_launch": fwd_bytes},
     }
     legs = {"fp32": dict(head, gbs=achieved, elements_per_s=E / (head["kernel_ms_mean"] * 1e-3))}
     outputs = {}
@@ -185,6 +222,25 @@ def main():
                 r, gbs=gbs, frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=lb,
                 elements_per_s=wl.mesh.n_elements / (r["kernel_ms_mean"] * 1e-3),
                 note="129 MB working set fits the 256 MB MALL: GB/s here is not HBM-only")
+        del Al
+        # 3D P2 Laplacian on the same unflattened cube (10 x 10 matrices)
+        A2 = torch.empty((wl.mesh.n_elements, 10, 10), dtype=torch.float32, device=dev)
+        pb = forward_bytes(wl.mesh.n_elements, wl.mesh.n_vertices, 10, 3, False)
+        for prec in ("fp32", "fp16x2"):
+            r = time_leg(lambda: fei.integrate(cl, kl, "laplace_p2", precision=prec, out=A2),
+                         args.steps, args.warmup, f"laplace_p2_3d_{prec}")
+            gbs = pb / (r["kernel_ms_mean"] * 1e-3) / 1e9
+            legs[f"laplace_p2_3d_{prec}"] = dict(
+                r, gbs=gbs, frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=pb,
+                elements_per_s=wl.mesh.n_elements / (r["kernel_ms_mean"] * 1e-3))
+        del A2
+    if args.copy_ref:
+        n = 512 * 2**20 // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        r = time_leg(lambda: dst.copy_(src), args.steps, args.warmup, "copy_512MiB")
+        legs["copy_512MiB_reference"] = dict(r, gbs=2 * n * 4 / (r["kernel_ms_mean"] * 1e-3) / 1e9)
+        del src, dst
     result["legs"] = legs
 
     # ---- CPU baseline: the FP64 oracle on the same workload ----------------
@@ -196,11 +252,18 @@ def main():
         t0 = time.perf_counter()
         Ao = oracle.integrate("elastic_p1", m.coords, m.conn, w.mu, w.lam)
         t1 = time.perf_counter()
+        # repeat whole passes until about 10 s of oracle time (bounded at 30 s)
+        reps, total = 1, t1 - t0
+        while total < 10.0 and total + (t1 - t0) < 30.0:
+            ta = time.perf_counter()
+            oracle.integrate("elastic_p1", m.coords, m.conn, w.mu, w.lam)
+            total += time.perf_counter() - ta
+            reps += 1
         result["cpu_baseline"] = {
-            "value": E / (t1 - t0), "unit": "element matrices/s", "cores": min(threads, cores),
-            "kind": "oracle",
-            "sample": f"the whole workload once ({E} elements), FP64 quadrature, "
-                      f"OpenMP over elements, {t1 - t0:.2f} s wall"}
+            "value": reps * E / total, "unit": "element matrices/s",
+            "cores": min(threads, cores), "kind": "oracle",
+            "sample": f"{reps} pass(es) over the whole workload ({E} elements each), FP64 "
+                      f"quadrature, OpenMP over elements, {total:.2f} s wall in total"}
         acc = {}
         for prec, Ag in outputs.items():
             if Ag is None:
