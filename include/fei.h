@@ -180,27 +180,61 @@ int fei_integrate_adjoint(const fei_mesh *m, int form, const float *mu,
 int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream);
 
 /* ---- heterogeneous batches ------------------------------------------------
- * Many meshes and forms integrated by one persistent launch captured in a HIP
- * graph (the paper's element batches, Sec. 4, applied across meshes).  The
- * plan owns only its descriptor table and graph; every pointer in the items
- * is caller memory that must outlive the plan.                              */
+ * Many meshes and forms integrated by one launch of a HIP graph (the paper's
+ * element batches, Sec. 4, applied across meshes).  Items are ordered
+ * heaviest first (algorithmic bytes) and cut into 256-element tiles.  Two
+ * graph shapes exist (fei_batch_config.mode):
+ *   0  one persistent kernel for all forms: workgroups take tiles from a
+ *      work counter (reset by a kernel node) until none are left;
+ *   1  one kernel per (form, dim) group, the groups captured as concurrent
+ *      branches of the graph (each kernel has the registers and LDS of its
+ *      own form only).
+ * fei_batch_tune times candidate configurations on the caller's data and
+ * rebuilds the graph with the fastest.
+ * The plan owns only its descriptor table, work counter, streams and graphs
+ * (allocated by fei_batch_create, released by fei_batch_destroy); every
+ * pointer in the items is caller memory that must outlive the plan.  Only
+ * FP32 coordinates are accepted in batches.                                */
 typedef struct fei_batch_item {
     fei_mesh mesh;
     int32_t form;
     int32_t pad_;
     const float *mu, *lam;  /* elasticity only */
     float *A;               /* forward output [E][n][n] */
-    const float *dA;        /* adjoint input (NULL if the adjoint is not used) */
+    const float *dA;        /* adjoint input; NULL leaves the item out of the adjoint */
     float *dx, *dy, *dz;    /* adjoint vertex gradients (accumulated) */
-    float *dmu, *dlam;      /* adjoint coefficient gradients (overwritten) */
+    float *dmu, *dlam;      /* adjoint coefficient gradients (overwritten, may be NULL) */
 } fei_batch_item;
+
+typedef struct fei_batch_config {
+    int32_t mode;           /* 0: persistent multi-form kernel, 1: per-group kernels */
+    int32_t variant;        /* output staging: 0 wide (LDS <= 64 KB per form), 1 narrow */
+    int32_t workgroups;     /* mode 0: persistent workgroups launched */
+    int32_t tiles_per_pop;  /* mode 0: tiles taken from the counter per atomic */
+    float ms;               /* measured time of this configuration (0: not tuned) */
+    int32_t reserved[3];
+} fei_batch_config;
 
 typedef struct fei_batch fei_batch;
 
-int fei_batch_create(const fei_batch_item *items, int n_items,
-                     const fei_options *opt, fei_batch **out);
+/* Validates every item, builds the plan and its graphs with the default
+ * configuration (mode 1, variant 0).  opt: precision and tau (NULL: defaults);
+ * the adjoint is FP32.  Does not touch the items' data.                     */
+int fei_batch_create(const fei_batch_item *items, int n_items, const fei_options *opt,
+                     fei_batch **out);
+/* One graph launch on `stream`: every item's forward (or adjoint).          */
 int fei_batch_run(fei_batch *b, void *stream);
 int fei_batch_run_adjoint(fei_batch *b, void *stream);
+/* Times the candidate configurations of the forward (adjoint = 0) or adjoint
+ * (adjoint = 1) graph on `stream` -- running them, so outputs are written,
+ * and for the adjoint dx/dy/dz receive one accumulation per trial -- then
+ * rebuilds that graph with the fastest.  *chosen (if not NULL) receives it. */
+int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *chosen);
+int fei_batch_get_config(const fei_batch *b, int adjoint, fei_batch_config *out);
+/* Rebuilds the forward/adjoint graph with a given configuration (for example
+ * one returned by an earlier fei_batch_tune).  mode 0 needs workgroups >= 1
+ * and tiles_per_pop >= 1; variant is 0 or 1.                                */
+int fei_batch_set_config(fei_batch *b, int adjoint, const fei_batch_config *cfg);
 int fei_batch_destroy(fei_batch *b);
 
 #ifdef __cplusplus

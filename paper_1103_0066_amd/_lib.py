@@ -23,7 +23,8 @@ F64 = 1
 EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_default",
            "fei_local_size", "fei_reference_tensor", "fei_reference_scale", "fei_integrate",
            "fei_integrate_adjoint", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
-           "fei_batch_run_adjoint", "fei_batch_destroy")
+           "fei_batch_run_adjoint", "fei_batch_tune", "fei_batch_get_config", "fei_batch_set_config",
+           "fei_batch_destroy")
 
 
 class FeiMesh(ctypes.Structure):
@@ -44,6 +45,17 @@ class FeiBatchItem(ctypes.Structure):
                 ("mu", ctypes.c_void_p), ("lam", ctypes.c_void_p), ("A", ctypes.c_void_p),
                 ("dA", ctypes.c_void_p), ("dx", ctypes.c_void_p), ("dy", ctypes.c_void_p),
                 ("dz", ctypes.c_void_p), ("dmu", ctypes.c_void_p), ("dlam", ctypes.c_void_p)]
+
+
+class FeiBatchConfig(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("tiles_per_pop", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+
+
+def config_dict(c: "FeiBatchConfig") -> dict:
+    return {"mode": c.mode, "variant": c.variant, "workgroups": c.workgroups,
+            "tiles_per_pop": c.tiles_per_pop, "ms": c.ms}
 
 
 class FeiError(RuntimeError):
@@ -88,6 +100,9 @@ def load():
     lib.fei_batch_run.argtypes = [vp, vp]
     lib.fei_batch_run_adjoint.argtypes = [vp, vp]
     lib.fei_batch_destroy.argtypes = [vp]
+    lib.fei_batch_tune.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(FeiBatchConfig)]
+    lib.fei_batch_get_config.argtypes = [vp, ctypes.c_int, ctypes.POINTER(FeiBatchConfig)]
+    lib.fei_batch_set_config.argtypes = [vp, ctypes.c_int, ctypes.POINTER(FeiBatchConfig)]
     for name in EXPORTS:
         getattr(lib, name)
     _lib = lib

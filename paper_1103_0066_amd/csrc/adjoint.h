@@ -257,128 +257,141 @@ __device__ __forceinline__ void scatter_vertices(const AdjParams &p, const int (
 }
 
 template <int FORM, int DIM, typename CT, int R>
-__global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p)
-{
+struct AdjTile {
     using T = Traits<FORM, DIM>;
     using S = Stage<FORM, DIM, R>;
     using AccT = typename std::conditional<sizeof(CT) == 8, double, float>::type;
-    constexpr int NN = S::NN;
-    constexpr int GP = ((T::G + 1) / 2) * 2;
-    constexpr int SW = (R > 0) ? ((64 * S::STR > NN) ? 64 * S::STR : NN) : ((NN + 3) / 4) * 4;
-    __shared__ __attribute__((aligned(16))) float s_stage[4][SW];
-    __shared__ double s_u64[4][GP];
-    __shared__ int s_key[4][kHashSlots];
-    __shared__ float s_val[4][kHashSlots * DIM];
+    static constexpr int NN = S::NN;
+    static constexpr int GP = ((T::G + 1) / 2) * 2;
+    static constexpr int SW = (R > 0) ? ((64 * S::STR > NN) ? 64 * S::STR : NN) : ((NN + 3) / 4) * 4;
+    // LDS: dA staging | FP64 fold of a flagged element | vertex-merge keys | values
+    static constexpr int OFF_U64 = 4 * SW * 4;
+    static constexpr int OFF_KEY = OFF_U64 + 4 * GP * 8;
+    static constexpr int OFF_VAL = OFF_KEY + 4 * kHashSlots * 4;
+    static constexpr int LDS_BYTES = OFF_VAL + 4 * kHashSlots * DIM * 4;
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t E = p.m.n_elements;
-    const int64_t e0 = blk * 256 + wave * 64;
-    const int64_t e = e0 + lane;
-    const bool valid = e < E;
-    float *st = s_stage[wave];
+    __device__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem)
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int64_t E = p.m.n_elements;
+        const int64_t e0 = blk * 256 + wave * 64;
+        const int64_t e = e0 + lane;
+        const bool valid = e < E;
+        float *st = reinterpret_cast<float *>(smem) + wave * SW;
+        double *u64 = reinterpret_cast<double *>(smem + OFF_U64) + wave * GP;
+        int *key = reinterpret_cast<int *>(smem + OFF_KEY) + wave * kHashSlots;
+        float *val = reinterpret_cast<float *>(smem + OFF_VAL) + wave * kHashSlots * DIM;
 
-    int v[DIM + 1] = {};
-    CT xv[DIM + 1][DIM] = {};
-    float mu = 0.f, lam = 0.f;
-    if (valid) {
-        load_conn<DIM>(p.m.conn, e, v);
-        gather<DIM>(p.m, v, xv);
+        int v[DIM + 1] = {};
+        CT xv[DIM + 1][DIM] = {};
+        float mu = 0.f, lam = 0.f;
+        if (valid) {
+            load_conn<DIM>(p.m.conn, e, v);
+            gather<DIM>(p.m, v, xv);
+            if constexpr (FORM == ELA1) {
+                mu = __builtin_nontemporal_load(p.mu + e);
+                lam = __builtin_nontemporal_load(p.lam + e);
+            }
+        }
+
+        // U = folded K^T applied to dA
+        AccT U[T::G];
+#pragma unroll
+        for (int g = 0; g < T::G; ++g) U[g] = AccT(0);
+        if constexpr (R > 0) {
+#pragma unroll
+            for (int c = 0; c < S::NCHUNK; ++c) {
+#pragma unroll
+                for (int k = 0; k < S::NV4; ++k) {
+                    const int f = lane + 64 * k;
+                    const int el = f / S::NV4, part = f - el * S::NV4;
+                    f32x4_t r = {0.f, 0.f, 0.f, 0.f};
+                    if (e0 + el < E)
+                        r = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(
+                            p.dA + (e0 + el) * (int64_t)NN + c * S::CH + 4 * part));
+                    *reinterpret_cast<f32x4_t *>(st + el * S::STR + 4 * part) = r;
+                }
+                wave_sync();
+#pragma unroll
+                for (int k = 0; k < S::CH; k += 4) {
+                    const f32x4_t w = *reinterpret_cast<const f32x4_t *>(st + lane * S::STR + k);
+                    const float r[4] = {w[0], w[1], w[2], w[3]};
+                    fold_piece<FORM, DIM, AccT>(U, c * S::CH + k, r, 4);
+                }
+                wave_sync();
+            }
+        } else if (valid) {
+            const float *__restrict__ dAe = p.dA + e * (int64_t)NN;
+#pragma unroll
+            for (int k = 0; k < NN; k += 4) {
+                float r[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (k + i < NN) r[i] = __builtin_nontemporal_load(dAe + k + i);
+                fold_piece<FORM, DIM, AccT>(U, k, r, NN - k < 4 ? NN - k : 4);
+            }
+        }
+
+        float Jbar[DIM][DIM], mubar = 0.f, lambar = 0.f;
+        bool flag = false, singular = false;
+        if constexpr (sizeof(CT) == 8) {
+            double J[DIM][DIM], adj[DIM][DIM];
+            jacobian<DIM>(xv, J);
+            const double det = adjugate(J, adj);
+            singular = valid && det == 0.0;
+            adjoint_chain<FORM, DIM>(adj, det, mu, lam, SRegs<FORM, DIM, AccT>{U}, Jbar, mubar, lambar);
+        } else {
+            float J[DIM][DIM], adj[DIM][DIM];
+            jacobian<DIM>(xv, J);
+            const float det = adjugate(J, adj);
+            flag = valid && needs_fp64<DIM>(J, adj, det, p.tau2);
+            if (!flag)
+                adjoint_chain<FORM, DIM>(adj, det, mu, lam, SRegs<FORM, DIM, AccT>{U}, Jbar, mubar,
+                                         lambar);
+            // flagged elements, one at a time: FP64 fold by the wave, FP64 chain by the owner
+            unsigned long long fm = __ballot(flag);
+            while (fm) {
+                const int L = __ffsll(fm) - 1;
+                fm &= fm - 1;
+                const int64_t eL = e0 + L;
+                for (int k = lane; k < NN; k += 64)
+                    st[k] = __builtin_nontemporal_load(p.dA + eL * (int64_t)NN + k);
+                wave_sync();
+                if (lane < T::G) {
+                    constexpr int NZ = KSparseShape<FORM, DIM>::NNZ;
+                    const KSparse<FORM, DIM> &ks = g_ksparse<FORM, DIM>;
+                    double u = 0.0;
+                    for (int t = 0; t < NZ; ++t)
+                        u += double(ks.coef[lane][t]) * double(st[ks.ij[lane][t]]);
+                    u64[lane] = u;
+                }
+                wave_sync();
+                if (lane == L) {
+                    double Jd[DIM][DIM], adjd[DIM][DIM];
+                    jacobian<DIM>(xv, Jd);
+                    const double detd = adjugate(Jd, adjd);
+                    singular = (detd == 0.0);
+                    adjoint_chain<FORM, DIM>(adjd, detd, mu, lam, SLds{u64, T::GD}, Jbar,
+                                             mubar, lambar);
+                }
+                wave_sync();
+            }
+        }
+        count_flags(p.counters, flag, singular);
         if constexpr (FORM == ELA1) {
-            mu = __builtin_nontemporal_load(p.mu + e);
-            lam = __builtin_nontemporal_load(p.lam + e);
+            if (valid && p.dmu) p.dmu[e] = mubar;
+            if (valid && p.dlam) p.dlam[e] = lambar;
         }
+        scatter_vertices<DIM>(p, v, Jbar, valid, key, val, lane);
     }
+};
 
-    // U = folded K^T applied to dA
-    AccT U[T::G];
-#pragma unroll
-    for (int g = 0; g < T::G; ++g) U[g] = AccT(0);
-    if constexpr (R > 0) {
-#pragma unroll
-        for (int c = 0; c < S::NCHUNK; ++c) {
-#pragma unroll
-            for (int k = 0; k < S::NV4; ++k) {
-                const int f = lane + 64 * k;
-                const int el = f / S::NV4, part = f - el * S::NV4;
-                f32x4_t r = {0.f, 0.f, 0.f, 0.f};
-                if (e0 + el < E)
-                    r = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(
-                        p.dA + (e0 + el) * (int64_t)NN + c * S::CH + 4 * part));
-                *reinterpret_cast<f32x4_t *>(st + el * S::STR + 4 * part) = r;
-            }
-            wave_sync();
-#pragma unroll
-            for (int k = 0; k < S::CH; k += 4) {
-                const f32x4_t w = *reinterpret_cast<const f32x4_t *>(st + lane * S::STR + k);
-                const float r[4] = {w[0], w[1], w[2], w[3]};
-                fold_piece<FORM, DIM, AccT>(U, c * S::CH + k, r, 4);
-            }
-            wave_sync();
-        }
-    } else if (valid) {
-        const float *__restrict__ dAe = p.dA + e * (int64_t)NN;
-#pragma unroll
-        for (int k = 0; k < NN; k += 4) {
-            float r[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (k + i < NN) r[i] = __builtin_nontemporal_load(dAe + k + i);
-            fold_piece<FORM, DIM, AccT>(U, k, r, NN - k < 4 ? NN - k : 4);
-        }
-    }
-
-    float Jbar[DIM][DIM], mubar = 0.f, lambar = 0.f;
-    bool flag = false, singular = false;
-    if constexpr (sizeof(CT) == 8) {
-        double J[DIM][DIM], adj[DIM][DIM];
-        jacobian<DIM>(xv, J);
-        const double det = adjugate(J, adj);
-        singular = valid && det == 0.0;
-        adjoint_chain<FORM, DIM>(adj, det, mu, lam, SRegs<FORM, DIM, AccT>{U}, Jbar, mubar, lambar);
-    } else {
-        float J[DIM][DIM], adj[DIM][DIM];
-        jacobian<DIM>(xv, J);
-        const float det = adjugate(J, adj);
-        flag = valid && needs_fp64<DIM>(J, adj, det, p.tau2);
-        if (!flag)
-            adjoint_chain<FORM, DIM>(adj, det, mu, lam, SRegs<FORM, DIM, AccT>{U}, Jbar, mubar,
-                                     lambar);
-        // flagged elements, one at a time: FP64 fold by the wave, FP64 chain by the owner
-        unsigned long long fm = __ballot(flag);
-        while (fm) {
-            const int L = __ffsll(fm) - 1;
-            fm &= fm - 1;
-            const int64_t eL = e0 + L;
-            for (int k = lane; k < NN; k += 64)
-                st[k] = __builtin_nontemporal_load(p.dA + eL * (int64_t)NN + k);
-            wave_sync();
-            if (lane < T::G) {
-                constexpr int NZ = KSparseShape<FORM, DIM>::NNZ;
-                const KSparse<FORM, DIM> &ks = g_ksparse<FORM, DIM>;
-                double u = 0.0;
-                for (int t = 0; t < NZ; ++t)
-                    u += double(ks.coef[lane][t]) * double(st[ks.ij[lane][t]]);
-                s_u64[wave][lane] = u;
-            }
-            wave_sync();
-            if (lane == L) {
-                double Jd[DIM][DIM], adjd[DIM][DIM];
-                jacobian<DIM>(xv, Jd);
-                const double detd = adjugate(Jd, adjd);
-                singular = (detd == 0.0);
-                adjoint_chain<FORM, DIM>(adjd, detd, mu, lam, SLds{s_u64[wave], T::GD}, Jbar,
-                                         mubar, lambar);
-            }
-            wave_sync();
-        }
-    }
-    count_flags(p.counters, flag, singular);
-    if constexpr (FORM == ELA1) {
-        if (valid && p.dmu) p.dmu[e] = mubar;
-        if (valid && p.dlam) p.dlam[e] = lambar;
-    }
-    scatter_vertices<DIM>(p, v, Jbar, valid, s_key[wave], s_val[wave], lane);
+template <int FORM, int DIM, typename CT, int R>
+__global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p)
+{
+    using Tile = AdjTile<FORM, DIM, CT, R>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
+    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
 }
 
 }  // namespace fei

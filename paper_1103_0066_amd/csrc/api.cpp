@@ -13,14 +13,15 @@
 #include "fei.h"
 #include "params.h"
 #include "shapes.h"
+#include "host.h"
 
 using namespace fei;
 
-namespace {
+namespace fei {
+namespace host {
 
 thread_local std::string g_last_error;
 
-int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int status, const char *fmt, ...)
 {
     char buf[512];
@@ -117,6 +118,13 @@ int check_coeffs(int form, const float *mu, const float *lam, int64_t E)
     }
     return FEI_OK;
 }
+
+}  // namespace host
+}  // namespace fei
+
+using namespace fei::host;
+
+namespace {
 
 // K of (form, dim) through the same functions the kernels' tables come from.
 template <typename F>

@@ -1,21 +1,404 @@
-// Heterogeneous batches (fei_batch_*).
+// Heterogeneous batches (fei_batch_*): plan construction, graph capture and
+// the autotuner over graph shapes.  Device code is in batch_dev.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
 #include "fei.h"
+#include "host.h"
+#include "params.h"
+#include "shapes.h"
+
+using namespace fei;
+using namespace fei::host;
+
+namespace {
+
+struct Group {
+    int form, dim;
+    int off, n;         // range in the grouped item array
+    int64_t tiles;
+};
+
+// One side (forward or adjoint) of a plan.
+struct Side {
+    std::vector<BatchItemDev> all;      // heaviest first, global tile numbering
+    std::vector<BatchItemDev> grouped;  // by (form, dim) group, per-group tile numbering
+    std::vector<Group> groups;
+    int64_t tiles = 0;
+    BatchItemDev *d_all = nullptr;
+    BatchItemDev *d_grouped = nullptr;
+    fei_batch_config cfg{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+double item_bytes(const fei_batch_item &it)
+{
+    const int n = local_size(it.form, it.mesh.dim);
+    const double per = 4.0 * (it.mesh.dim + 1) + (it.form == FEI_ELASTIC_P1 ? 8.0 : 0.0) + 4.0 * n * n;
+    return per * double(it.mesh.n_elements) + 4.0 * it.mesh.dim * double(it.mesh.n_vertices);
+}
+
+int64_t tiles_of(int64_t E) { return (E + 255) / 256; }
+
+}  // namespace
+
+struct fei_batch {
+    int device = 0;
+    int n_cu = 0;
+    int precision = 0;
+    Side side[2];
+    int32_t *d_counter = nullptr;  // [0] forward, [1] adjoint
+    hipStream_t cap = nullptr;
+    hipStream_t branch[6] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[6] = {};
+};
+
+namespace {
+
+int upload(const std::vector<BatchItemDev> &v, BatchItemDev **dst)
+{
+    if (v.empty()) return FEI_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), v.size() * sizeof(BatchItemDev));
+    if (e != hipSuccess) return fail(FEI_ENOMEM, "batch descriptors: %s", hipGetErrorString(e));
+    e = hipMemcpy(*dst, v.data(), v.size() * sizeof(BatchItemDev), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptors upload");
+    return FEI_OK;
+}
+
+// Orders a side heaviest first (globally and within groups) and numbers tiles.
+void layout(Side &sd, std::vector<std::pair<double, BatchItemDev>> items)
+{
+    std::stable_sort(items.begin(), items.end(),
+                     [](const auto &a, const auto &b) { return a.first > b.first; });
+    int64_t t = 0;
+    for (auto &it : items) {
+        BatchItemDev d = it.second;
+        d.tile_begin = t;
+        t += tiles_of(d.fp.m.n_elements);
+        sd.all.push_back(d);
+    }
+    sd.tiles = t;
+    // groups by (form, dim), heaviest group first
+    std::vector<std::pair<double, int>> keys;
+    for (auto &it : items) {
+        const int key = it.second.form * 4 + it.second.dim;
+        auto f = std::find_if(keys.begin(), keys.end(), [&](auto &k) { return k.second == key; });
+        if (f == keys.end()) keys.push_back({it.first, key});
+        else f->first += it.first;
+    }
+    std::stable_sort(keys.begin(), keys.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    for (auto &k : keys) {
+        Group g{k.second / 4, k.second % 4, int(sd.grouped.size()), 0, 0};
+        for (auto &it : items) {
+            if (it.second.form * 4 + it.second.dim != k.second) continue;
+            BatchItemDev d = it.second;
+            d.tile_begin = g.tiles;
+            g.tiles += tiles_of(d.fp.m.n_elements);
+            sd.grouped.push_back(d);
+            ++g.n;
+        }
+        sd.groups.push_back(g);
+    }
+}
+
+// Enqueues one run of a side with configuration c on stream s.
+hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t s)
+{
+    Side &sd = b->side[adj];
+    const int prec = adj ? int(P_FP32) : b->precision;
+    if (sd.tiles == 0) return hipSuccess;
+    if (c.mode == 0) {
+        BatchLaunch L{sd.d_all, int32_t(sd.all.size()), c.tiles_per_pop, sd.tiles, b->d_counter + adj};
+        hipError_t e = launch_batch_reset(L.counter, s);
+        if (e != hipSuccess) return e;
+        return launch_batch(adj != 0, prec, c.variant, L, c.workgroups, s);
+    }
+    hipError_t e = hipEventRecord(b->fork, s);
+    if (e != hipSuccess) return e;
+    for (size_t g = 0; g < sd.groups.size(); ++g) {
+        const Group &G = sd.groups[g];
+        hipStream_t bs = b->branch[g];
+        if ((e = hipStreamWaitEvent(bs, b->fork, 0)) != hipSuccess) return e;
+        BatchLaunch L{sd.d_grouped + G.off, G.n, 1, G.tiles, nullptr};
+        if ((e = launch_batch_group(adj != 0, G.form, G.dim, prec, c.variant, L, bs)) != hipSuccess)
+            return e;
+        if ((e = hipEventRecord(b->join[g], bs)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, b->join[g], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void drop_graph(Side &sd)
+{
+    if (sd.exec) hipGraphExecDestroy(sd.exec);
+    if (sd.graph) hipGraphDestroy(sd.graph);
+    sd.exec = nullptr;
+    sd.graph = nullptr;
+}
+
+int build_graph(fei_batch *b, int adj)
+{
+    Side &sd = b->side[adj];
+    drop_graph(sd);
+    if (sd.tiles == 0) return FEI_OK;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = enqueue(b, adj, sd.cfg, b->cap);
+    e = hipStreamEndCapture(b->cap, &sd.graph);
+    if (le != hipSuccess) {
+        drop_graph(sd);
+        return hip_fail(le, "batch capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&sd.exec, sd.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(sd);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return FEI_OK;
+}
+
+void release(fei_batch *b)
+{
+    for (Side &sd : b->side) {
+        drop_graph(sd);
+        if (sd.d_all) hipFree(sd.d_all);
+        if (sd.d_grouped) hipFree(sd.d_grouped);
+    }
+    if (b->d_counter) hipFree(b->d_counter);
+    for (hipStream_t s : b->branch)
+        if (s) hipStreamDestroy(s);
+    for (hipEvent_t ev : b->join)
+        if (ev) hipEventDestroy(ev);
+    if (b->fork) hipEventDestroy(b->fork);
+    if (b->cap) hipStreamDestroy(b->cap);
+    delete b;
+}
+
+int check_item(const fei_batch_item &it, int k, MeshView &mv)
+{
+    int rc = check_mesh(&it.mesh, mv);
+    if (rc) return fail(rc, "item %d: %s", k, fei_last_error());
+    if (!valid_form(it.form)) return fail(FEI_EINVAL, "item %d: unknown form %d", k, it.form);
+    if (it.mesh.coord_dtype != FEI_F32)
+        return fail(FEI_EUNSUPPORTED, "item %d: batches take FP32 coordinates", k);
+    if ((rc = check_coeffs(it.form, it.mu, it.lam, it.mesh.n_elements)))
+        return fail(rc, "item %d: %s", k, fei_last_error());
+    if (it.mesh.n_elements > 0 && (!it.A || !aligned(it.A, 16)))
+        return fail(FEI_EINVAL, "item %d: A NULL or not 16-byte aligned", k);
+    if (it.dA) {
+        if (!aligned(it.dA, 16)) return fail(FEI_EINVAL, "item %d: dA not 16-byte aligned", k);
+        if (!it.dx || !it.dy || (it.mesh.dim == 3 && !it.dz))
+            return fail(FEI_EINVAL, "item %d: adjoint needs dx, dy (, dz)", k);
+        if (it.form != FEI_ELASTIC_P1 && (it.dmu || it.dlam))
+            return fail(FEI_EINVAL, "item %d: dmu/dlam only for elasticity", k);
+    }
+    return FEI_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
-struct fei_batch {
-    int unused;
-};
-
-int fei_batch_create(const fei_batch_item *, int, const fei_options *, fei_batch **out)
+int fei_batch_create(const fei_batch_item *items, int n_items, const fei_options *opt,
+                     fei_batch **out)
 {
-    if (out) *out = nullptr;
-    return FEI_EUNSUPPORTED;
+    if (!out) return fail(FEI_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(FEI_EINVAL, "bad item list");
+    fei_options o = opt ? *opt : defaults();
+    int rc = check_options(o);
+    if (rc) return rc;
+    const float tau2 = tau2_of(o.tau);
+
+    std::vector<std::pair<double, BatchItemDev>> fwd, adj;
+    for (int k = 0; k < n_items; ++k) {
+        const fei_batch_item &it = items[k];
+        MeshView mv;
+        if ((rc = check_item(it, k, mv))) return rc;
+        if (it.mesh.n_elements == 0) continue;
+        BatchItemDev d;
+        std::memset(&d, 0, sizeof d);
+        d.form = it.form;
+        d.dim = it.mesh.dim;
+        d.fp.m = mv;
+        d.fp.mu = it.mu;
+        d.fp.lam = it.lam;
+        d.fp.A = it.A;
+        d.fp.counters = o.counters;
+        d.fp.tau2 = tau2;
+        d.ap.m = mv;
+        d.ap.mu = it.mu;
+        d.ap.lam = it.lam;
+        d.ap.dA = it.dA;
+        d.ap.dx = it.dx;
+        d.ap.dy = it.dy;
+        d.ap.dz = it.mesh.dim == 3 ? it.dz : nullptr;
+        d.ap.dmu = it.dmu;
+        d.ap.dlam = it.dlam;
+        d.ap.counters = o.counters;
+        d.ap.tau2 = tau2;
+        const double w = item_bytes(it);
+        fwd.push_back({w, d});
+        if (it.dA) adj.push_back({w, d});
+    }
+
+    fei_batch *b = new (std::nothrow) fei_batch();
+    if (!b) return fail(FEI_ENOMEM, "plan allocation");
+    b->precision = o.precision;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "device query");
+    }
+    layout(b->side[0], fwd);
+    layout(b->side[1], adj);
+    for (int s = 0; s < 2; ++s) {
+        Side &sd = b->side[s];
+        if ((rc = upload(sd.all, &sd.d_all)) || (rc = upload(sd.grouped, &sd.d_grouped))) {
+            release(b);
+            return rc;
+        }
+        sd.cfg.mode = 1;
+        sd.cfg.variant = 0;
+        sd.cfg.workgroups = 2 * b->n_cu;
+        sd.cfg.tiles_per_pop = 1;
+        sd.cfg.ms = 0.f;
+    }
+    if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_counter), 2 * sizeof(int32_t))) != hipSuccess) {
+        release(b);
+        return fail(FEI_ENOMEM, "work counter: %s", hipGetErrorString(e));
+    }
+    if ((e = hipMemset(b->d_counter, 0, 2 * sizeof(int32_t))) == hipSuccess &&
+        (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) == hipSuccess &&
+        (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) == hipSuccess) {
+        for (int g = 0; g < 6 && e == hipSuccess; ++g) {
+            e = hipStreamCreateWithFlags(&b->branch[g], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[g], hipEventDisableTiming);
+        }
+    }
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "plan streams/events");
+    }
+    for (int s = 0; s < 2; ++s) {
+        if ((rc = build_graph(b, s))) {
+            release(b);
+            return rc;
+        }
+    }
+    *out = b;
+    return FEI_OK;
 }
-int fei_batch_run(fei_batch *, void *) { return FEI_EUNSUPPORTED; }
-int fei_batch_run_adjoint(fei_batch *, void *) { return FEI_EUNSUPPORTED; }
-int fei_batch_destroy(fei_batch *) { return FEI_OK; }
+
+int fei_batch_run(fei_batch *b, void *stream)
+{
+    if (!b) return fail(FEI_EINVAL, "plan is NULL");
+    if (!b->side[0].exec) return FEI_OK;  // no elements
+    hipError_t e = hipGraphLaunch(b->side[0].exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FEI_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+int fei_batch_run_adjoint(fei_batch *b, void *stream)
+{
+    if (!b) return fail(FEI_EINVAL, "plan is NULL");
+    if (!b->side[1].exec) return FEI_OK;  // no adjoint items
+    hipError_t e = hipGraphLaunch(b->side[1].exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FEI_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+int fei_batch_get_config(const fei_batch *b, int adjoint, fei_batch_config *out)
+{
+    if (!b || !out || (adjoint != 0 && adjoint != 1)) return fail(FEI_EINVAL, "bad argument");
+    *out = b->side[adjoint].cfg;
+    return FEI_OK;
+}
+
+int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *chosen)
+{
+    if (!b || (adjoint != 0 && adjoint != 1)) return fail(FEI_EINVAL, "bad argument");
+    Side &sd = b->side[adjoint];
+    if (sd.tiles == 0) {
+        if (chosen) *chosen = sd.cfg;
+        return FEI_OK;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<fei_batch_config> cand;
+    for (int var = 0; var < 2; ++var) {
+        fei_batch_config c{};
+        c.mode = 1;
+        c.variant = var;
+        c.workgroups = 0;
+        c.tiles_per_pop = 1;
+        cand.push_back(c);
+        for (int wg : {1, 2, 4})
+            for (int pop : {1, 4}) {
+                fei_batch_config p{};
+                p.mode = 0;
+                p.variant = var;
+                p.workgroups = wg * b->n_cu;
+                p.tiles_per_pop = pop;
+                cand.push_back(p);
+            }
+    }
+    hipEvent_t t0, t1;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    int best = -1;
+    float best_ms = 0.f;
+    for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
+        if (enqueue(b, adjoint, cand[k], s) != hipSuccess) continue;  // warm-up
+        float times[3];
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+            e = hipEventRecord(t0, s);
+            if (e == hipSuccess) e = enqueue(b, adjoint, cand[k], s);
+            if (e == hipSuccess) e = hipEventRecord(t1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&times[r], t0, t1);
+        }
+        if (e != hipSuccess) break;
+        std::sort(times, times + 3);
+        cand[k].ms = times[1];
+        if (best < 0 || times[1] < best_ms) {
+            best = int(k);
+            best_ms = times[1];
+        }
+    }
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_fail(e, "tuning run");
+    if (best < 0) return fail(FEI_EDEVICE, "no batch configuration could be launched");
+    sd.cfg = cand[best];
+    int rc = build_graph(b, adjoint);
+    if (rc) return rc;
+    if (chosen) *chosen = sd.cfg;
+    return FEI_OK;
+}
+
+int fei_batch_set_config(fei_batch *b, int adjoint, const fei_batch_config *cfg)
+{
+    if (!b || !cfg || (adjoint != 0 && adjoint != 1)) return fail(FEI_EINVAL, "bad argument");
+    if ((cfg->mode != 0 && cfg->mode != 1) || (cfg->variant != 0 && cfg->variant != 1))
+        return fail(FEI_EINVAL, "mode and variant must be 0 or 1");
+    if (cfg->mode == 0 && (cfg->workgroups < 1 || cfg->tiles_per_pop < 1))
+        return fail(FEI_EINVAL, "mode 0 needs workgroups >= 1 and tiles_per_pop >= 1");
+    b->side[adjoint].cfg = *cfg;
+    return build_graph(b, adjoint);
+}
+
+int fei_batch_destroy(fei_batch *b)
+{
+    if (b) release(b);
+    return FEI_OK;
+}
 
 }  // extern "C"

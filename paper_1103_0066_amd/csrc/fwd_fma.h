@@ -132,73 +132,87 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One workgroup tile (256 elements, 4 waves) of the FP32 forward.  LDS comes
+// from the caller (LDS_BYTES, 16-byte aligned), so one persistent kernel can
+// host the tiles of several forms.
+template <int FORM, int DIM, typename CT, int R>
+struct FwdFmaTile {
+    using T = Traits<FORM, DIM>;
+    using S = Stage<FORM, DIM, R>;
+    static constexpr int LDS_BYTES = (R > 0) ? 4 * 64 * S::STR * 4 : 0;
+
+    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    {
+        const int64_t E = p.m.n_elements;
+        const int64_t e = blk * 256 + threadIdx.x;
+        if constexpr (R == 0) {
+            if (e >= E) return;
+        }
+        const bool valid = e < E;
+        float Gf[T::G];
+        bool flag = false, singular = false;
+        if (valid) {
+            int v[DIM + 1];
+            load_conn<DIM>(p.m.conn, e, v);
+            CT xv[DIM + 1][DIM];
+            gather<DIM>(p.m, v, xv);
+            float mu = 0.f, lam = 0.f;
+            if constexpr (FORM == ELA1) {
+                mu = __builtin_nontemporal_load(p.mu + e);
+                lam = __builtin_nontemporal_load(p.lam + e);
+            }
+            flag = geometry<FORM, DIM>(xv, mu, lam, p.tau2, Gf, singular);
+        } else {
+#pragma unroll
+            for (int g = 0; g < T::G; ++g) Gf[g] = 0.f;
+        }
+        count_flags(p.counters, flag, singular);
+        float Au[Unique<FORM, DIM>::NU];
+        unique_entries<FORM, DIM>(Gf, Au);
+
+        if constexpr (R == 0) {
+            contract_store<FORM, DIM>(Au, p.A + e * (int64_t)S::NN);
+        } else {
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            float *st = reinterpret_cast<float *>(smem) + wave * 64 * S::STR;
+            const int64_t e0 = blk * 256 + wave * 64;
+#pragma unroll
+            for (int c = 0; c < S::NCHUNK; ++c) {
+                // this lane's R rows into its LDS row
+#pragma unroll
+                for (int k = 0; k < S::CH; k += 4) {
+                    f32x4_t r;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int flat = c * S::CH + k + i;
+                        r[i] = Au[sym_index(S::N, flat / S::N, flat % S::N)];
+                    }
+                    *reinterpret_cast<f32x4_t *>(st + lane * S::STR + k) = r;
+                }
+                wave_sync();
+                // cooperative store of the wave's chunk: piece f -> (element, part)
+#pragma unroll
+                for (int k = 0; k < S::NV4; ++k) {
+                    const int f = lane + 64 * k;
+                    const int el = f / S::NV4, part = f - el * S::NV4;
+                    const f32x4_t r =
+                        *reinterpret_cast<const f32x4_t *>(st + el * S::STR + 4 * part);
+                    if (e0 + el < E)
+                        store_out(reinterpret_cast<f32x4_t *>(p.A + (e0 + el) * (int64_t)S::NN +
+                                                              c * S::CH + 4 * part), r);
+                }
+                wave_sync();
+            }
+        }
+    }
+};
+
 template <int FORM, int DIM, typename CT, int R>
 __global__ __launch_bounds__(256) void fwd_fma_kernel(FwdParams p)
 {
-    using T = Traits<FORM, DIM>;
-    using S = Stage<FORM, DIM, R>;
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t E = p.m.n_elements;
-    const int64_t e = blk * 256 + threadIdx.x;
-    if constexpr (R == 0) {
-        if (e >= E) return;
-    }
-    const bool valid = e < E;
-    float Gf[T::G];
-    bool flag = false, singular = false;
-    if (valid) {
-        int v[DIM + 1];
-        load_conn<DIM>(p.m.conn, e, v);
-        CT xv[DIM + 1][DIM];
-        gather<DIM>(p.m, v, xv);
-        float mu = 0.f, lam = 0.f;
-        if constexpr (FORM == ELA1) {
-            mu = __builtin_nontemporal_load(p.mu + e);
-            lam = __builtin_nontemporal_load(p.lam + e);
-        }
-        flag = geometry<FORM, DIM>(xv, mu, lam, p.tau2, Gf, singular);
-    } else {
-#pragma unroll
-        for (int g = 0; g < T::G; ++g) Gf[g] = 0.f;
-    }
-    count_flags(p.counters, flag, singular);
-    float Au[Unique<FORM, DIM>::NU];
-    unique_entries<FORM, DIM>(Gf, Au);
-
-    if constexpr (R == 0) {
-        contract_store<FORM, DIM>(Au, p.A + e * (int64_t)S::NN);
-    } else {
-        __shared__ __attribute__((aligned(16))) float s_stage[4][64 * S::STR];
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        float *st = s_stage[wave];
-        const int64_t e0 = blk * 256 + wave * 64;
-#pragma unroll
-        for (int c = 0; c < S::NCHUNK; ++c) {
-            // this lane's R rows into its LDS row
-#pragma unroll
-            for (int k = 0; k < S::CH; k += 4) {
-                f32x4_t r;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int flat = c * S::CH + k + i;
-                    r[i] = Au[sym_index(S::N, flat / S::N, flat % S::N)];
-                }
-                *reinterpret_cast<f32x4_t *>(st + lane * S::STR + k) = r;
-            }
-            wave_sync();
-            // cooperative store of the wave's chunk: piece f -> (element, part)
-#pragma unroll
-            for (int k = 0; k < S::NV4; ++k) {
-                const int f = lane + 64 * k;
-                const int el = f / S::NV4, part = f - el * S::NV4;
-                const f32x4_t r = *reinterpret_cast<const f32x4_t *>(st + el * S::STR + 4 * part);
-                if (e0 + el < E)
-                    *reinterpret_cast<f32x4_t *>(p.A + (e0 + el) * (int64_t)S::NN + c * S::CH +
-                                                 4 * part) = r;
-            }
-            wave_sync();
-        }
-    }
+    using Tile = FwdFmaTile<FORM, DIM, CT, R>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES > 0 ? Tile::LDS_BYTES : 16];
+    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
 }
 
 }  // namespace fei

@@ -110,132 +110,146 @@ struct MfmaLds {
 };
 
 template <int FORM, int DIM, typename CT, int PREC, bool DIRECT>
-__global__ __launch_bounds__(256) void fwd_mfma_kernel(FwdParams p)
-{
+struct MfmaTile {
     using T = Traits<FORM, DIM>;
     using S = MfmaShape<FORM, DIM, PREC>;
     using L = MfmaLds<FORM, DIM, PREC>;
-    __shared__ uint4 s_frag[S::NFRAG];
-    __shared__ __attribute__((aligned(16))) unsigned char s_wave[4][L::WBYTES];
-    __shared__ int s_exp[256];
+    static constexpr int FRAG_BYTES = S::NFRAG * 16;
+    static constexpr int LDS_BYTES = FRAG_BYTES + 4 * L::WBYTES + 256 * 4;
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    uint16_t *s_b = reinterpret_cast<uint16_t *>(s_wave[wave]);
-    // stage the K fragments (read-only, L2-resident table)
-    const uint4 *gfr = reinterpret_cast<const uint4 *>(g_frags<FORM, DIM, PREC>.v);
-    for (int i = tid; i < S::NFRAG; i += 256) s_frag[i] = gfr[i];
-
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t e0 = blk * 256 + wave * 64;
-    const int64_t E = p.m.n_elements;
-
-    // phase 1: geometry, one lane per element
+    // LDS: K fragments | per-wave split-Gf rows / output staging | FP16 exponents
+    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
     {
-        const int64_t e = e0 + lane;
-        float Gf[T::G];
-        bool flag = false, singular = false;
-        if (e < E) {
-            int v[DIM + 1];
-            load_conn<DIM>(p.m.conn, e, v);
-            CT xv[DIM + 1][DIM];
-            gather<DIM>(p.m, v, xv);
-            float mu = 0.f, lam = 0.f;
-            if constexpr (FORM == ELA1) {
-                mu = __builtin_nontemporal_load(p.mu + e);
-                lam = __builtin_nontemporal_load(p.lam + e);
-            }
-            flag = geometry<FORM, DIM>(xv, mu, lam, p.tau2, Gf, singular);
-        } else {
-#pragma unroll
-            for (int g = 0; g < T::G; ++g) Gf[g] = 0.f;
-        }
-        count_flags(p.counters, flag, singular);
-        s_exp[tid] = split_gf<FORM, DIM, PREC>(Gf, s_b + lane * S::BROW);
-    }
-    __syncthreads();
+        uint4 *s_frag = reinterpret_cast<uint4 *>(smem);
+        unsigned char *s_wave_base = smem + FRAG_BYTES;
+        int *s_exp = reinterpret_cast<int *>(smem + FRAG_BYTES + 4 * L::WBYTES);
 
-    // phase 2: the wave's 64 elements as 4 MFMA column groups of 16
-    const int n = lane & 15, q = lane >> 4;
-    uint4 bf[4][S::KS];
-    int ex[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int el = g * 16 + n;
-#pragma unroll
-        for (int s = 0; s < S::KS; ++s)
-            bf[g][s] = *reinterpret_cast<const uint4 *>(s_b + el * S::BROW + 32 * s + 8 * q);
-        ex[g] = s_exp[wave * 64 + el];
-    }
-    if constexpr (DIRECT || !L::STAGED) {
-        // each lane stores its 4 consecutive entries of one element per M tile
-#pragma unroll
-        for (int t = 0; t < S::MT; ++t) {
-            floatx4_t acc[4];
-#pragma unroll
-            for (int g = 0; g < 4; ++g) acc[g] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int s = 0; s < S::KS; ++s) {
-                const uint4 a = s_frag[(t * S::KS + s) * 64 + lane];
-#pragma unroll
-                for (int g = 0; g < 4; ++g) acc[g] = mfma_step<PREC>(a, bf[g][s], acc[g]);
-            }
-            const int m0 = 16 * t + 4 * q;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int64_t e = e0 + g * 16 + n;
-                if (e >= E) continue;
-                floatx4_t r = acc[g];
-                if constexpr (PREC == P_FP16X2) {
-                    r[0] = ldexpf(r[0], ex[g]); r[1] = ldexpf(r[1], ex[g]);
-                    r[2] = ldexpf(r[2], ex[g]); r[3] = ldexpf(r[3], ex[g]);
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        unsigned char *s_wave_w = s_wave_base + wave * L::WBYTES;
+        uint16_t *s_b = reinterpret_cast<uint16_t *>(s_wave_w);
+        // stage the K fragments (read-only, L2-resident table)
+        const uint4 *gfr = reinterpret_cast<const uint4 *>(g_frags<FORM, DIM, PREC>.v);
+        for (int i = tid; i < S::NFRAG; i += 256) s_frag[i] = gfr[i];
+
+        const int64_t e0 = blk * 256 + wave * 64;
+        const int64_t E = p.m.n_elements;
+
+        // phase 1: geometry, one lane per element
+        {
+            const int64_t e = e0 + lane;
+            float Gf[T::G];
+            bool flag = false, singular = false;
+            if (e < E) {
+                int v[DIM + 1];
+                load_conn<DIM>(p.m.conn, e, v);
+                CT xv[DIM + 1][DIM];
+                gather<DIM>(p.m, v, xv);
+                float mu = 0.f, lam = 0.f;
+                if constexpr (FORM == ELA1) {
+                    mu = __builtin_nontemporal_load(p.mu + e);
+                    lam = __builtin_nontemporal_load(p.lam + e);
                 }
-                float *Ae = p.A + e * (int64_t)S::NN;
-                if constexpr (S::NN % 4 == 0) {
-                    if (m0 < S::NN)
-                        *reinterpret_cast<float4 *>(Ae + m0) = make_float4(r[0], r[1], r[2], r[3]);
-                } else {
+                flag = geometry<FORM, DIM>(xv, mu, lam, p.tau2, Gf, singular);
+            } else {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (m0 + i < S::NN) Ae[m0 + i] = r[i];
-                }
+                for (int g = 0; g < T::G; ++g) Gf[g] = 0.f;
             }
+            count_flags(p.counters, flag, singular);
+            s_exp[tid] = split_gf<FORM, DIM, PREC>(Gf, s_b + lane * S::BROW);
         }
-    } else {
-        // per column group: all M tiles into LDS, then contiguous 16-byte stores
-        float *so = reinterpret_cast<float *>(s_wave[wave]);
-        wave_sync();  // the B fragments above have been read from this region
+        __syncthreads();
+
+        // phase 2: the wave's 64 elements as 4 MFMA column groups of 16
+        const int n = lane & 15, q = lane >> 4;
+        uint4 bf[4][S::KS];
+        int ex[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
+            const int el = g * 16 + n;
+#pragma unroll
+            for (int s = 0; s < S::KS; ++s)
+                bf[g][s] = *reinterpret_cast<const uint4 *>(s_b + el * S::BROW + 32 * s + 8 * q);
+            ex[g] = s_exp[wave * 64 + el];
+        }
+        if constexpr (DIRECT || !L::STAGED) {
+            // each lane stores its 4 consecutive entries of one element per M tile
 #pragma unroll
             for (int t = 0; t < S::MT; ++t) {
-                floatx4_t acc = floatx4_t{0.f, 0.f, 0.f, 0.f};
+                floatx4_t acc[4];
 #pragma unroll
-                for (int s = 0; s < S::KS; ++s)
-                    acc = mfma_step<PREC>(s_frag[(t * S::KS + s) * 64 + lane], bf[g][s], acc);
-                const int m0 = 16 * t + 4 * q;
-                if constexpr (PREC == P_FP16X2) {
-                    acc[0] = ldexpf(acc[0], ex[g]); acc[1] = ldexpf(acc[1], ex[g]);
-                    acc[2] = ldexpf(acc[2], ex[g]); acc[3] = ldexpf(acc[3], ex[g]);
+                for (int g = 0; g < 4; ++g) acc[g] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < S::KS; ++s) {
+                    const uint4 a = s_frag[(t * S::KS + s) * 64 + lane];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) acc[g] = mfma_step<PREC>(a, bf[g][s], acc[g]);
                 }
-                if (m0 < S::NN)
-                    *reinterpret_cast<floatx4_t *>(so + n * L::OSTR + m0) = acc;
-            }
-            wave_sync();
-            constexpr int NV4 = S::NN / 4;      // 16-byte pieces per element
-            const int64_t eg = e0 + g * 16;
-            float *dst = p.A + eg * (int64_t)S::NN;
+                const int m0 = 16 * t + 4 * q;
 #pragma unroll
-            for (int k = 0; k < (16 * NV4 + 63) / 64; ++k) {
-                const int f = lane + 64 * k;
-                if (f >= 16 * NV4) break;
-                const int el = f / NV4, part = f - el * NV4;
-                const floatx4_t r = *reinterpret_cast<const floatx4_t *>(so + el * L::OSTR + 4 * part);
-                if (eg + el < E) *reinterpret_cast<floatx4_t *>(dst + 4 * f) = r;
+                for (int g = 0; g < 4; ++g) {
+                    const int64_t e = e0 + g * 16 + n;
+                    if (e >= E) continue;
+                    floatx4_t r = acc[g];
+                    if constexpr (PREC == P_FP16X2) {
+                        r[0] = ldexpf(r[0], ex[g]); r[1] = ldexpf(r[1], ex[g]);
+                        r[2] = ldexpf(r[2], ex[g]); r[3] = ldexpf(r[3], ex[g]);
+                    }
+                    float *Ae = p.A + e * (int64_t)S::NN;
+                    if constexpr (S::NN % 4 == 0) {
+                        if (m0 < S::NN)
+                            *reinterpret_cast<float4 *>(Ae + m0) = make_float4(r[0], r[1], r[2], r[3]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (m0 + i < S::NN) Ae[m0 + i] = r[i];
+                    }
+                }
             }
-            wave_sync();
+        } else {
+            // per column group: all M tiles into LDS, then contiguous 16-byte stores
+            float *so = reinterpret_cast<float *>(s_wave_w);
+            wave_sync();  // the B fragments above have been read from this region
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+#pragma unroll
+                for (int t = 0; t < S::MT; ++t) {
+                    floatx4_t acc = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int s = 0; s < S::KS; ++s)
+                        acc = mfma_step<PREC>(s_frag[(t * S::KS + s) * 64 + lane], bf[g][s], acc);
+                    const int m0 = 16 * t + 4 * q;
+                    if constexpr (PREC == P_FP16X2) {
+                        acc[0] = ldexpf(acc[0], ex[g]); acc[1] = ldexpf(acc[1], ex[g]);
+                        acc[2] = ldexpf(acc[2], ex[g]); acc[3] = ldexpf(acc[3], ex[g]);
+                    }
+                    if (m0 < S::NN)
+                        *reinterpret_cast<floatx4_t *>(so + n * L::OSTR + m0) = acc;
+                }
+                wave_sync();
+                constexpr int NV4 = S::NN / 4;      // 16-byte pieces per element
+                const int64_t eg = e0 + g * 16;
+                float *dst = p.A + eg * (int64_t)S::NN;
+#pragma unroll
+                for (int k = 0; k < (16 * NV4 + 63) / 64; ++k) {
+                    const int f = lane + 64 * k;
+                    if (f >= 16 * NV4) break;
+                    const int el = f / NV4, part = f - el * NV4;
+                    const floatx4_t r = *reinterpret_cast<const floatx4_t *>(so + el * L::OSTR + 4 * part);
+                    if (eg + el < E) store_out(reinterpret_cast<f32x4_t *>(dst + 4 * f), r);
+                }
+                wave_sync();
+            }
         }
     }
+};
+
+template <int FORM, int DIM, typename CT, int PREC, bool DIRECT>
+__global__ __launch_bounds__(256) void fwd_mfma_kernel(FwdParams p)
+{
+    using Tile = MfmaTile<FORM, DIM, CT, PREC, DIRECT>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
+    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
 }
 
 }  // namespace fei

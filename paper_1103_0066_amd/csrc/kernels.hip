@@ -4,6 +4,7 @@
 #include <type_traits>
 
 #include "adjoint.h"
+#include "batch_dev.h"
 #include "fwd_fma.h"
 #include "fwd_mfma.h"
 
@@ -51,14 +52,16 @@ constexpr bool rows_ok()
     return R == 0 || (N % R == 0 && (R * N) % 4 == 0 && 4 * 64 * (R * N + 4) * 4 <= 160 * 1024);
 }
 
-// Tuned defaults of the staging rows.  Forward: whole matrices (measured
-// fastest for every form on MI355X); adjoint: a third of them or less, which
-// leaves LDS room for the vertex-merge table.
+// Tuned defaults of the staging rows (measured on MI355X).  Forward: whole
+// matrices, except 3D elasticity where 4-row chunks keep LDS at 53 KB per
+// workgroup (3 workgroups per CU) and beat whole 151 KB matrices; adjoint: a
+// third of the matrix or less, leaving LDS room for the vertex-merge table.
 template <int F, int D>
 constexpr int default_rows()
 {
     constexpr int N = Traits<F, D>::N;
-    return (N * N) % 4 == 0 && N % 4 != 3 ? N : 0;
+    if constexpr (N == 12) return 4;
+    return (N * N) % 4 == 0 ? N : 0;
 }
 
 template <int F, int D>
@@ -197,6 +200,121 @@ AdjLauncher find_adjoint(const Variant &v)
         }
     }
     return nullptr;
+}
+
+namespace {
+
+template <int PREC, int VAR>
+hipError_t launch_batch_fwd(const BatchLaunch &b, int grid, hipStream_t s)
+{
+    constexpr int lds = batch_fwd_lds<PREC, VAR>();
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_fwd_kernel<PREC, VAR>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batch_fwd_kernel<PREC, VAR>), dim3(grid), dim3(kBlock), lds, s, b);
+    return hipGetLastError();
+}
+
+template <int VAR>
+hipError_t launch_batch_adj(const BatchLaunch &b, int grid, hipStream_t s)
+{
+    constexpr int lds = batch_adj_lds<VAR>();
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_adj_kernel<VAR>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batch_adj_kernel<VAR>), dim3(grid), dim3(kBlock), lds, s, b);
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_batch_fwd_var(const BatchLaunch &b, int variant, int grid, hipStream_t s)
+{
+    return variant == 0 ? launch_batch_fwd<PREC, 0>(b, grid, s) : launch_batch_fwd<PREC, 1>(b, grid, s);
+}
+
+}  // namespace
+
+size_t batch_lds_bytes(bool adjoint, int precision, int variant)
+{
+    if (variant != 0 && variant != 1) return 0;
+    if (adjoint) return precision == P_FP32 ? (variant ? batch_adj_lds<1>() : batch_adj_lds<0>()) : 0;
+    switch (precision) {
+    case P_FP32: return variant ? batch_fwd_lds<P_FP32, 1>() : batch_fwd_lds<P_FP32, 0>();
+    case P_FP16X2: return variant ? batch_fwd_lds<P_FP16X2, 1>() : batch_fwd_lds<P_FP16X2, 0>();
+    case P_BF16X2: return variant ? batch_fwd_lds<P_BF16X2, 1>() : batch_fwd_lds<P_BF16X2, 0>();
+    case P_BF16X3: return variant ? batch_fwd_lds<P_BF16X3, 1>() : batch_fwd_lds<P_BF16X3, 0>();
+    default: return 0;
+    }
+}
+
+hipError_t launch_batch(bool adjoint, int precision, int variant, const BatchLaunch &b, int grid,
+                        hipStream_t s)
+{
+    if (adjoint) return variant ? launch_batch_adj<1>(b, grid, s) : launch_batch_adj<0>(b, grid, s);
+    switch (precision) {
+    case P_FP32: return launch_batch_fwd_var<P_FP32>(b, variant, grid, s);
+    case P_FP16X2: return launch_batch_fwd_var<P_FP16X2>(b, variant, grid, s);
+    case P_BF16X2: return launch_batch_fwd_var<P_BF16X2>(b, variant, grid, s);
+    case P_BF16X3: return launch_batch_fwd_var<P_BF16X3>(b, variant, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+
+template <int F, int D, int PREC, int VAR, bool ADJ>
+hipError_t launch_group(const BatchLaunch &b, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_group_kernel<F, D, PREC, VAR, ADJ>), dim3(unsigned(b.n_tiles)),
+                       dim3(kBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+template <int F, int D, int PREC>
+hipError_t launch_group_pv(bool adj, int variant, const BatchLaunch &b, hipStream_t s)
+{
+    if (adj) {
+        if constexpr (PREC == P_FP32)
+            return variant ? launch_group<F, D, P_FP32, 1, true>(b, s)
+                           : launch_group<F, D, P_FP32, 0, true>(b, s);
+        else return hipErrorInvalidValue;
+    }
+    return variant ? launch_group<F, D, PREC, 1, false>(b, s) : launch_group<F, D, PREC, 0, false>(b, s);
+}
+
+template <int F, int D>
+hipError_t launch_group_fd(bool adj, int precision, int variant, const BatchLaunch &b, hipStream_t s)
+{
+    switch (precision) {
+    case P_FP32: return launch_group_pv<F, D, P_FP32>(adj, variant, b, s);
+    case P_FP16X2: return launch_group_pv<F, D, P_FP16X2>(adj, variant, b, s);
+    case P_BF16X2: return launch_group_pv<F, D, P_BF16X2>(adj, variant, b, s);
+    case P_BF16X3: return launch_group_pv<F, D, P_BF16X3>(adj, variant, b, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_group(bool adjoint, int form, int dim, int precision, int variant,
+                              const BatchLaunch &b, hipStream_t s)
+{
+    if (b.n_tiles <= 0) return hipSuccess;
+    switch (form * 4 + dim) {
+    case LAP1 * 4 + 2: return launch_group_fd<LAP1, 2>(adjoint, precision, variant, b, s);
+    case LAP1 * 4 + 3: return launch_group_fd<LAP1, 3>(adjoint, precision, variant, b, s);
+    case ELA1 * 4 + 2: return launch_group_fd<ELA1, 2>(adjoint, precision, variant, b, s);
+    case ELA1 * 4 + 3: return launch_group_fd<ELA1, 3>(adjoint, precision, variant, b, s);
+    case LAP2 * 4 + 2: return launch_group_fd<LAP2, 2>(adjoint, precision, variant, b, s);
+    case LAP2 * 4 + 3: return launch_group_fd<LAP2, 3>(adjoint, precision, variant, b, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_reset(int32_t *counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
 }
 
 hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad_dev,

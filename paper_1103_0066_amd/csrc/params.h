@@ -49,6 +49,34 @@ using AdjLauncher = hipError_t (*)(const AdjParams &, hipStream_t);
 FwdLauncher find_forward(const Variant &v);
 AdjLauncher find_adjoint(const Variant &v);
 
+// Heterogeneous batch: one work item per (mesh, form), laid out for the
+// persistent batch kernels.
+struct BatchItemDev {
+    int32_t form;        // fei::Form
+    int32_t dim;
+    int64_t tile_begin;  // first global tile (256 elements) of this item
+    FwdParams fp;
+    AdjParams ap;
+};
+
+struct BatchLaunch {
+    const BatchItemDev *items;  // device, sorted by tile_begin
+    int32_t n_items;
+    int32_t tiles_per_pop;
+    int64_t n_tiles;
+    int32_t *counter;           // device work counter, reset by launch_batch_reset
+};
+
+// Dynamic LDS bytes of a batch kernel variant; 0 if the variant does not exist.
+size_t batch_lds_bytes(bool adjoint, int precision, int variant);
+hipError_t launch_batch(bool adjoint, int precision, int variant, const BatchLaunch &b, int grid,
+                        hipStream_t s);
+hipError_t launch_batch_reset(int32_t *counter, hipStream_t s);
+// One (form, dim) group of a batch: b.items holds only that group's items and
+// b.n_tiles its tiles (one workgroup per tile).
+hipError_t launch_batch_group(bool adjoint, int form, int dim, int precision, int variant,
+                              const BatchLaunch &b, hipStream_t s);
+
 // Device-side connectivity check: writes the count of entries outside
 // [0, n_vertices) into *n_bad_dev (int64, zeroed by the kernel's caller).
 hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad_dev,

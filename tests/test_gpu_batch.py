@@ -1,0 +1,166 @@
+"""Heterogeneous batches: one graph launch over many meshes and forms must give
+what per-mesh launches give, in every graph shape, replay after replay."""
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+from gpu_util import TOL, TOL_VERTEX, element_errors, vertex_scale
+
+pytestmark = pytest.mark.gpu
+
+fei = pytest.importorskip("paper_1103_0066_amd")
+
+DEV = "cuda"
+
+
+def _items(seed=0, with_adjoint=False):
+    """Every (form, dim) with ragged sizes, one empty and one single-element item."""
+    specs = [("laplace_p1", meshgen.square_mesh(13, 0.2, 61, np.float32)),
+             ("laplace_p1", meshgen.cube_mesh(5, 4, 4, 0.15, 62)),
+             ("elastic_p1", meshgen.square_mesh(11, 0.2, 63, np.float32)),
+             ("elastic_p1", meshgen.flatten_elements(meshgen.cube_mesh(6, 5, 4, 0.15, 64), 7, 65)),
+             ("laplace_p2", meshgen.square_mesh(9, 0.2, 66, np.float32)),
+             ("laplace_p2", meshgen.cube_mesh(4, 4, 3, 0.15, 67)),
+             ("elastic_p1", meshgen.cube_mesh(1, 1, 1, 0.1, 68)),
+             ("laplace_p1", meshgen.cube_mesh(2, 2, 2, 0.1, 69))]
+    items, host = [], []
+    for k, (form, m) in enumerate(specs):
+        if k == 6:
+            m = meshgen.Mesh(m.coords, m.conn[:1].copy())           # E = 1
+        if k == 7:
+            m = meshgen.Mesh(m.coords, m.conn[:0].copy())           # E = 0
+        it = {"form": form, "coords": torch.from_numpy(m.soa()).to(DEV),
+              "conn": torch.from_numpy(m.conn).to(DEV)}
+        mu = lam = None
+        if form == "elastic_p1":
+            mu, lam = meshgen.lame(m.n_elements, 70 + k)
+            it["mu"], it["lam"] = torch.from_numpy(mu).to(DEV), torch.from_numpy(lam).to(DEV)
+        if with_adjoint:
+            n = fei.local_size(form, m.dim)
+            dA = meshgen.upstream(m.n_elements, n, 80 + k)
+            it["dA"] = torch.from_numpy(dA).to(DEV)
+            it["dcoords"] = torch.zeros((m.dim, m.n_vertices), dtype=torch.float32, device=DEV)
+            if form == "elastic_p1":
+                it["dmu"] = torch.empty(m.n_elements, dtype=torch.float32, device=DEV)
+                it["dlam"] = torch.empty(m.n_elements, dtype=torch.float32, device=DEV)
+        items.append(it)
+        host.append((form, m, mu, lam))
+    return items, host
+
+
+CONFIGS = [{"mode": 1, "variant": 0}, {"mode": 1, "variant": 1},
+           {"mode": 0, "variant": 0, "workgroups": 256, "tiles_per_pop": 1},
+           {"mode": 0, "variant": 1, "workgroups": 512, "tiles_per_pop": 4},
+           {"mode": 0, "variant": 0, "workgroups": 3, "tiles_per_pop": 2}]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16x2", "bf16x3"])
+def test_batch_forward_matches_per_mesh_launches(precision):
+    items, host = _items()
+    eager = [fei.integrate(it["coords"], it["conn"], it["form"], it.get("mu"), it.get("lam"),
+                           precision=precision).cpu().numpy() for it in items]
+    b = fei.Batch(items, precision=precision)
+    for cfg in CONFIGS:
+        b.set_config(cfg)
+        for rep in range(3):                       # graph replays, eager work between them
+            for it in items:
+                it["A"].fill_(float("nan"))
+            torch.cuda.synchronize()
+            b.run()
+            torch.cuda.synchronize()
+            for k, it in enumerate(items):
+                got = it["A"].cpu().numpy()
+                assert np.array_equal(got.view(np.uint32), eager[k].view(np.uint32)), (cfg, rep, k)
+    for (form, m, mu, lam), it in zip(host, items):
+        if m.n_elements:
+            Ao = oracle.integrate(form, m.coords, m.conn, mu, lam)
+            assert element_errors(it["A"].cpu().numpy(), Ao).max() <= TOL[precision]
+    b.close()
+
+
+def test_batch_adjoint_matches_oracle():
+    items, host = _items(with_adjoint=True)
+    b = fei.Batch(items)
+    for cfg in CONFIGS:
+        b.set_config(cfg, adjoint=True)
+        for it in items:
+            it["dcoords"].zero_()
+        torch.cuda.synchronize()
+        b.run_adjoint()
+        torch.cuda.synchronize()
+        for (form, m, mu, lam), it in zip(host, items):
+            if m.n_elements == 0:
+                assert float(it["dcoords"].abs().max()) == 0.0
+                continue
+            dA = it["dA"].cpu().numpy()
+            gv, gm, gl, _ = oracle.gradient(form, m.coords, m.conn, dA, mu, lam)
+            go = oracle.vertex_gradient(gv, m.conn, m.n_vertices)
+            sc = vertex_scale(gv, m.conn, m.n_vertices)
+            g = it["dcoords"].cpu().numpy().T
+            used = sc > 0
+            assert (np.abs(g - go).max(axis=1)[used] / sc[used]).max() <= TOL_VERTEX, (cfg, form)
+            if form == "elastic_p1":
+                ref = fei.integrate_adjoint(it["coords"], it["conn"], form, it["dA"], it["mu"],
+                                            it["lam"])
+                assert np.array_equal(it["dmu"].cpu().numpy(), ref[1].cpu().numpy())
+    b.close()
+
+
+def test_batch_tune_picks_a_working_configuration():
+    items, host = _items(with_adjoint=True)
+    eager = [fei.integrate(it["coords"], it["conn"], it["form"], it.get("mu"),
+                           it.get("lam")).cpu().numpy() for it in items]
+    b = fei.Batch(items)
+    cfg = b.tune()
+    assert cfg["ms"] > 0 and cfg["mode"] in (0, 1)
+    assert b.config() == cfg
+    for it in items:
+        it["A"].zero_()
+    b.run()
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        assert np.array_equal(it["A"].cpu().numpy().view(np.uint32), eager[k].view(np.uint32))
+    acfg = b.tune(adjoint=True)
+    assert acfg["ms"] > 0
+    b.close()
+
+
+def test_batch_rejects_bad_items():
+    items, _ = _items()
+    bad = dict(items[0])
+    bad["coords"] = bad["coords"].double()
+    with pytest.raises(fei.FeiError):
+        fei.Batch([bad])
+    with pytest.raises(fei.FeiError):
+        fei.Batch([{"form": "laplace_p1", "coords": items[3]["coords"], "conn": items[3]["conn"],
+                    "mu": items[3]["mu"]}])
+
+
+def test_heterogeneous_workload_sampled():
+    """The 64-mesh heterogeneous workload (bench.py's batch leg), sampled against the oracle."""
+    wl = meshgen.batch_items()
+    items = []
+    for w in wl:
+        it = {"form": w.form, "coords": torch.from_numpy(w.mesh.soa()).to(DEV),
+              "conn": torch.from_numpy(w.mesh.conn).to(DEV)}
+        if w.mu is not None:
+            it["mu"], it["lam"] = torch.from_numpy(w.mu).to(DEV), torch.from_numpy(w.lam).to(DEV)
+        items.append(it)
+    b = fei.Batch(items)
+    b.tune()
+    for it in items:
+        it["A"].fill_(float("nan"))
+    b.run()
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(3))
+    for w, it in zip(wl, items):
+        E = w.mesh.n_elements
+        idx = np.union1d(rng.choice(E, size=min(200, E), replace=False), [0, E - 1])
+        A = it["A"][torch.from_numpy(idx).to(DEV)].cpu().numpy()
+        Ao = oracle.integrate(w.form, w.mesh.coords, w.mesh.conn[idx], 
+                              None if w.mu is None else w.mu[idx],
+                              None if w.lam is None else w.lam[idx])
+        assert element_errors(A, Ao).max() <= TOL["fp32"], w.name
+    b.close()
