@@ -107,35 +107,60 @@ struct MfmaLds {
     static constexpr int BBYTES = 64 * S::BROW * 2;           // split-Gf rows of a wave
     static constexpr int OBYTES = STAGED ? 16 * OSTR * 4 : 0;  // 16 staged matrices
     static constexpr int WBYTES = ((BBYTES > OBYTES ? BBYTES : OBYTES) + 15) / 16 * 16;
+    // K fragments live in registers when they take at most 128 VGPRs, else in LDS
+    static constexpr bool AREG = S::MT * S::KS <= 32;
 };
 
+// One workgroup tile (256 elements, 4 waves) of the MFMA forward.  Waves only
+// touch their own LDS rows, so the phases are ordered per wave, not per
+// workgroup; the K fragments are loaded once (load_frags) and reused for
+// every tile a persistent workgroup processes.
 template <int FORM, int DIM, typename CT, int PREC, bool DIRECT>
 struct MfmaTile {
     using T = Traits<FORM, DIM>;
     using S = MfmaShape<FORM, DIM, PREC>;
     using L = MfmaLds<FORM, DIM, PREC>;
-    static constexpr int FRAG_BYTES = S::NFRAG * 16;
+    static constexpr int FRAG_BYTES = L::AREG ? 0 : S::NFRAG * 16;
     static constexpr int LDS_BYTES = FRAG_BYTES + 4 * L::WBYTES + 256 * 4;
 
-    // LDS: K fragments | per-wave split-Gf rows / output staging | FP16 exponents
-    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
-    {
-        uint4 *s_frag = reinterpret_cast<uint4 *>(smem);
-        unsigned char *s_wave_base = smem + FRAG_BYTES;
-        int *s_exp = reinterpret_cast<int *>(smem + FRAG_BYTES + 4 * L::WBYTES);
+    struct Frags {
+        uint4 v[L::AREG ? S::MT * S::KS : 1];
+    };
 
+    // K fragments into registers, or (too many for registers) into LDS with a
+    // workgroup barrier; call once per workgroup before run().
+    __device__ static void load_frags(Frags &a, unsigned char *smem)
+    {
+        const uint4 *gfr = reinterpret_cast<const uint4 *>(g_frags<FORM, DIM, PREC>.v);
+        if constexpr (L::AREG) {
+            const int lane = threadIdx.x & 63;
+#pragma unroll
+            for (int i = 0; i < S::MT * S::KS; ++i) a.v[i] = gfr[i * 64 + lane];
+        } else {
+            uint4 *s_frag = reinterpret_cast<uint4 *>(smem);
+            for (int i = threadIdx.x; i < S::NFRAG; i += 256) s_frag[i] = gfr[i];
+            __syncthreads();
+        }
+    }
+
+    __device__ static uint4 frag(const Frags &a, const unsigned char *smem, int t, int s)
+    {
+        if constexpr (L::AREG) return a.v[t * S::KS + s];
+        else return reinterpret_cast<const uint4 *>(smem)[(t * S::KS + s) * 64 + (threadIdx.x & 63)];
+    }
+
+    // LDS: [K fragments] | per-wave split-Gf rows / output staging | FP16 exponents
+    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem, const Frags &a)
+    {
         const int tid = threadIdx.x;
         const int lane = tid & 63, wave = tid >> 6;
-        unsigned char *s_wave_w = s_wave_base + wave * L::WBYTES;
+        unsigned char *s_wave_w = smem + FRAG_BYTES + wave * L::WBYTES;
         uint16_t *s_b = reinterpret_cast<uint16_t *>(s_wave_w);
-        // stage the K fragments (read-only, L2-resident table)
-        const uint4 *gfr = reinterpret_cast<const uint4 *>(g_frags<FORM, DIM, PREC>.v);
-        for (int i = tid; i < S::NFRAG; i += 256) s_frag[i] = gfr[i];
-
+        int *s_exp = reinterpret_cast<int *>(smem + FRAG_BYTES + 4 * L::WBYTES) + wave * 64;
         const int64_t e0 = blk * 256 + wave * 64;
         const int64_t E = p.m.n_elements;
 
-        // phase 1: geometry, one lane per element
+        // phase 1: geometry, one lane per element, split Gf into this wave's rows
         {
             const int64_t e = e0 + lane;
             float Gf[T::G];
@@ -156,9 +181,9 @@ struct MfmaTile {
                 for (int g = 0; g < T::G; ++g) Gf[g] = 0.f;
             }
             count_flags(p.counters, flag, singular);
-            s_exp[tid] = split_gf<FORM, DIM, PREC>(Gf, s_b + lane * S::BROW);
+            s_exp[lane] = split_gf<FORM, DIM, PREC>(Gf, s_b + lane * S::BROW);
         }
-        __syncthreads();
+        wave_sync();
 
         // phase 2: the wave's 64 elements as 4 MFMA column groups of 16
         const int n = lane & 15, q = lane >> 4;
@@ -170,8 +195,9 @@ struct MfmaTile {
 #pragma unroll
             for (int s = 0; s < S::KS; ++s)
                 bf[g][s] = *reinterpret_cast<const uint4 *>(s_b + el * S::BROW + 32 * s + 8 * q);
-            ex[g] = s_exp[wave * 64 + el];
+            ex[g] = s_exp[el];
         }
+        wave_sync();  // the B fragments have been read; the rows may be reused
         if constexpr (DIRECT || !L::STAGED) {
             // each lane stores its 4 consecutive entries of one element per M tile
 #pragma unroll
@@ -181,9 +207,9 @@ struct MfmaTile {
                 for (int g = 0; g < 4; ++g) acc[g] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int s = 0; s < S::KS; ++s) {
-                    const uint4 a = s_frag[(t * S::KS + s) * 64 + lane];
+                    const uint4 af = frag(a, smem, t, s);
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) acc[g] = mfma_step<PREC>(a, bf[g][s], acc[g]);
+                    for (int g = 0; g < 4; ++g) acc[g] = mfma_step<PREC>(af, bf[g][s], acc[g]);
                 }
                 const int m0 = 16 * t + 4 * q;
 #pragma unroll
@@ -198,7 +224,7 @@ struct MfmaTile {
                     float *Ae = p.A + e * (int64_t)S::NN;
                     if constexpr (S::NN % 4 == 0) {
                         if (m0 < S::NN)
-                            *reinterpret_cast<float4 *>(Ae + m0) = make_float4(r[0], r[1], r[2], r[3]);
+                            store_out(reinterpret_cast<f32x4_t *>(Ae + m0), r);
                     } else {
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
@@ -209,7 +235,6 @@ struct MfmaTile {
         } else {
             // per column group: all M tiles into LDS, then contiguous 16-byte stores
             float *so = reinterpret_cast<float *>(s_wave_w);
-            wave_sync();  // the B fragments above have been read from this region
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
 #pragma unroll
@@ -217,7 +242,7 @@ struct MfmaTile {
                     floatx4_t acc = floatx4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int s = 0; s < S::KS; ++s)
-                        acc = mfma_step<PREC>(s_frag[(t * S::KS + s) * 64 + lane], bf[g][s], acc);
+                        acc = mfma_step<PREC>(frag(a, smem, t, s), bf[g][s], acc);
                     const int m0 = 16 * t + 4 * q;
                     if constexpr (PREC == P_FP16X2) {
                         acc[0] = ldexpf(acc[0], ex[g]); acc[1] = ldexpf(acc[1], ex[g]);
@@ -227,7 +252,7 @@ struct MfmaTile {
                         *reinterpret_cast<floatx4_t *>(so + n * L::OSTR + m0) = acc;
                 }
                 wave_sync();
-                constexpr int NV4 = S::NN / 4;      // 16-byte pieces per element
+                constexpr int NV4 = S::NN / 4;  // 16-byte pieces per element
                 const int64_t eg = e0 + g * 16;
                 float *dst = p.A + eg * (int64_t)S::NN;
 #pragma unroll
@@ -235,21 +260,52 @@ struct MfmaTile {
                     const int f = lane + 64 * k;
                     if (f >= 16 * NV4) break;
                     const int el = f / NV4, part = f - el * NV4;
-                    const floatx4_t r = *reinterpret_cast<const floatx4_t *>(so + el * L::OSTR + 4 * part);
+                    const floatx4_t r =
+                        *reinterpret_cast<const floatx4_t *>(so + el * L::OSTR + 4 * part);
                     if (eg + el < E) store_out(reinterpret_cast<f32x4_t *>(dst + 4 * f), r);
                 }
                 wave_sync();
             }
         }
     }
+
+    // One tile without preloaded fragments (batch kernels).
+    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    {
+        Frags a;
+        load_frags(a, smem);
+        run(p, blk, smem, a);
+    }
+};
+
+// Tiles of a persistent workgroup: the tiles are split into contiguous
+// ranges, one per XCD that has workgroups (workgroups are dispatched
+// round-robin over the 8 XCDs), and the workgroups of an XCD stride through
+// its range.  With G < 8 workgroups only XCDs 0..G-1 get a range.
+struct PersistentTiles {
+    int64_t begin, end, stride;
+    __device__ PersistentTiles(int64_t n_tiles)
+    {
+        const int64_t G = gridDim.x, b = blockIdx.x;
+        const int64_t X = G < 8 ? G : 8;
+        const int64_t x = b % 8, i = b / 8;
+        const int64_t cnt = G / 8 + (x < G % 8 ? 1 : 0);
+        const int64_t r0 = x * n_tiles / X, r1 = (x + 1) * n_tiles / X;
+        begin = r0 + i;
+        end = r1;
+        stride = cnt;
+    }
 };
 
 template <int FORM, int DIM, typename CT, int PREC, bool DIRECT>
-__global__ __launch_bounds__(256) void fwd_mfma_kernel(FwdParams p)
+__global__ __launch_bounds__(256) void fwd_mfma_kernel(FwdParams p, int64_t n_tiles)
 {
     using Tile = MfmaTile<FORM, DIM, CT, PREC, DIRECT>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
-    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
+    typename Tile::Frags a;
+    Tile::load_frags(a, smem);
+    const PersistentTiles pt(n_tiles);
+    for (int64_t t = pt.begin; t < pt.end; t += pt.stride) Tile::run(p, t, smem, a);
 }
 
 }  // namespace fei

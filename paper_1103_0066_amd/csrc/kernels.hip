@@ -27,11 +27,29 @@ hipError_t launch_fwd_fma(const FwdParams &p, hipStream_t s)
     return hipGetLastError();
 }
 
+// Persistent grid: as many workgroups as fit on the device at once (queried
+// once per kernel), at most one per tile.
+template <typename K>
+int persistent_grid(K kernel, int64_t n_tiles)
+{
+    static const int64_t resident = [&]() -> int64_t {
+        int dev = 0, blocks = 0, n_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, kBlock, 0) != hipSuccess ||
+            blocks < 1 || n_cu < 1)
+            return 256;
+        return int64_t(blocks) * n_cu;
+    }();
+    return int(resident < n_tiles ? resident : n_tiles);
+}
+
 template <int F, int D, typename CT, int PREC, bool DIRECT>
 hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
 {
-    hipLaunchKernelGGL((fwd_mfma_kernel<F, D, CT, PREC, DIRECT>), dim3(grid_for(p.m.n_elements)),
-                       dim3(kBlock), 0, s, p);
+    const int64_t n_tiles = (p.m.n_elements + kBlock - 1) / kBlock;
+    auto k = fwd_mfma_kernel<F, D, CT, PREC, DIRECT>;
+    hipLaunchKernelGGL(k, dim3(persistent_grid(k, n_tiles)), dim3(kBlock), 0, s, p, n_tiles);
     return hipGetLastError();
 }
 

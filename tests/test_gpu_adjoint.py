@@ -31,10 +31,17 @@ def _case(name):
     raise KeyError(name)
 
 
+def _nan_coeff_buffers(mesh, form):
+    if form != "elastic_p1":
+        return {}
+    return {k: torch.full((mesh.n_elements,), float("nan"), device="cuda") for k in ("dmu", "dlam")}
+
+
 def _gpu_adjoint(mesh, form, mu, lam, dA):
     coords, conn = mesh_to_device(mesh)
     dc, dmu, dlam = fei.integrate_adjoint(coords, conn, form, vec_to_device(dA),
-                                          vec_to_device(mu), vec_to_device(lam))
+                                          vec_to_device(mu), vec_to_device(lam),
+                                          **_nan_coeff_buffers(mesh, form))
     torch.cuda.synchronize()
     g = dc.cpu().numpy().T.astype(np.float64)      # [N_v, dim]
     return (g, None if dmu is None else dmu.cpu().numpy(),
@@ -92,7 +99,7 @@ def test_adjoint_staging_modes(case, rows):
     for r in (rows, 0):
         dc, dmu, dlam = fei.integrate_adjoint(coords, conn, form, vec_to_device(dA),
                                               vec_to_device(mu), vec_to_device(lam),
-                                              store_rows=r)
+                                              store_rows=r, **_nan_coeff_buffers(mesh, form))
         outs.append((dc.cpu().numpy().T.astype(np.float64),
                      None if dmu is None else dmu.cpu().numpy()))
     gv, gm, gl, _ = oracle.gradient(form, mesh.coords, mesh.conn, dA, mu, lam)
@@ -162,7 +169,9 @@ def test_full_adjoint_sampled_and_invariants():
     coords, conn = mesh_to_device(m)
     mu, lam = vec_to_device(w.mu), vec_to_device(w.lam)
     dA = vec_to_device(w.dA)
-    dc, dmu, dlam = fei.integrate_adjoint(coords, conn, w.form, dA, mu, lam)
+    dc, dmu, dlam = fei.integrate_adjoint(coords, conn, w.form, dA, mu, lam,
+                                          **_nan_coeff_buffers(m, w.form))
+    assert not bool(torch.isnan(dmu).any() or torch.isnan(dlam).any())
     A = fei.integrate(coords, conn, w.form, mu, lam)
     L = float((A.double() * dA.double()).sum())
     # invariants

@@ -48,9 +48,12 @@ CASES = ["lap2d_f64", "lap2d_f32", "lap3d", "elast3d", "elast2d", "p2_3d", "p2_2
 
 
 def _run(mesh, form, mu, lam, precision, **kw):
+    """Integrate into a NaN-filled output, so an element the kernel misses shows."""
     coords, conn = mesh_to_device(mesh)
+    n = fei.local_size(form, mesh.dim)
+    out = torch.full((mesh.n_elements, n, n), float("nan"), device=coords.device)
     A = fei.integrate(coords, conn, form, vec_to_device(mu), vec_to_device(lam),
-                      precision=precision, **kw)
+                      precision=precision, out=out, **kw)
     torch.cuda.synchronize()
     return A.cpu().numpy()
 
@@ -90,6 +93,20 @@ def test_forward_staging_modes(case, precision, rows):
     assert np.array_equal(A.view(np.uint32), A0.view(np.uint32))
 
 
+@pytest.mark.parametrize("precision,rows", [("fp32", 0), ("fp32", -1), ("fp16x2", 0),
+                                            ("fp16x2", -1), ("bf16x3", 0)])
+def test_every_tile_count_is_covered(precision, rows):
+    """1 to 10 workgroup tiles (persistent kernels split tiles over the XCDs that
+    have workgroups): every element written, every element right."""
+    m = meshgen.flatten_elements(meshgen.cube_mesh(8, 8, 8, 0.15, 21), 20, 22)
+    mu, lam = meshgen.lame(m.n_elements, 23)
+    for E in (1, 255, 256, 257, 3 * 256 + 5, 7 * 256, 8 * 256 + 1, 9 * 256 + 100, 2600):
+        sub = meshgen.Mesh(m.coords, np.ascontiguousarray(m.conn[:E]))
+        A = _run(sub, "elastic_p1", mu[:E], lam[:E], precision, store_rows=rows)
+        Ao = oracle.integrate("elastic_p1", m.coords, sub.conn, mu[:E], lam[:E])
+        assert element_errors(A, Ao).max() <= TOL[precision], E
+
+
 def test_unsupported_staging_is_rejected():
     mesh, form, mu, lam = _case("elast3d")
     coords, conn = mesh_to_device(mesh)
@@ -116,9 +133,11 @@ def test_empty_and_single_element(precision):
     assert A0.shape == (0, 12, 12)
     for e in (0, int(mesh.flattened[0])):
         one = mesh.conn[e:e + 1]
-        A1 = fei.integrate(coords, torch.from_numpy(one).to(coords.device), form,
-                           vec_to_device(mu[e:e + 1]), vec_to_device(lam[e:e + 1]),
-                           precision=precision).cpu().numpy()
+        A1 = torch.full((1, 12, 12), float("nan"), device=coords.device)
+        fei.integrate(coords, torch.from_numpy(one).to(coords.device), form,
+                      vec_to_device(mu[e:e + 1]), vec_to_device(lam[e:e + 1]),
+                      precision=precision, out=A1)
+        A1 = A1.cpu().numpy()
         Ao = oracle.integrate(form, mesh.coords, one, mu[e:e + 1], lam[e:e + 1])
         assert element_errors(A1, Ao).max() <= TOL[precision]
 
@@ -196,8 +215,10 @@ def test_full_elasticity_sampled(precision):
     m = w.mesh
     print(f"[full] {w.name} {precision}", flush=True)
     coords, conn = mesh_to_device(m)
-    A = fei.integrate(coords, conn, w.form, vec_to_device(w.mu), vec_to_device(w.lam),
-                      precision=precision)
+    A = torch.full((m.n_elements, 12, 12), float("nan"), device=coords.device)
+    fei.integrate(coords, conn, w.form, vec_to_device(w.mu), vec_to_device(w.lam),
+                  precision=precision, out=A)
+    assert not bool(torch.isnan(A).any())
     idx = _sample(m.n_elements, m.flattened, 20000, 7)
     As = A[torch.from_numpy(idx).to(A.device)].cpu().numpy()
     Ao = oracle.integrate(w.form, m.coords, m.conn[idx], w.mu[idx], w.lam[idx])
@@ -220,7 +241,9 @@ def test_full_laplace3d_sampled(precision):
     w = meshgen.lap3d(64)
     m = w.mesh
     coords, conn = mesh_to_device(m)
-    A = fei.integrate(coords, conn, w.form, precision=precision)
+    A = torch.full((m.n_elements, 4, 4), float("nan"), device=coords.device)
+    fei.integrate(coords, conn, w.form, precision=precision, out=A)
+    assert not bool(torch.isnan(A).any())
     idx = _sample(m.n_elements, None, 20000, 8)
     As = A[torch.from_numpy(idx).to(A.device)].cpu().numpy()
     Ao = oracle.integrate(w.form, m.coords, m.conn[idx])
@@ -233,6 +256,7 @@ def test_full_laplace2d_every_element():
     w = meshgen.lap2d(64)
     m = w.mesh
     coords, conn = mesh_to_device(m)
-    A = fei.integrate(coords, conn, w.form).cpu().numpy()
+    A = torch.full((m.n_elements, 3, 3), float("nan"), device=coords.device)
+    A = fei.integrate(coords, conn, w.form, out=A).cpu().numpy()
     Ao = oracle.integrate(w.form, m.coords, m.conn)
     assert element_errors(A, Ao).max() <= TOL["fp32"]
