@@ -9,10 +9,10 @@
 // which is the paper's per-entry contraction of a d x d block of G with a
 // d x d block of K (Sec. 4.3), executed sequentially by the lane for the
 // n(n+1)/2 distinct entries of its (symmetric) element matrix.  K is the same
-// for every lane of the grid, so it lives in a __constant__ table and reaches
-// the lanes through the scalar data cache as SGPR operands of v_fma_f32: a
-// wave-uniform broadcast is what the scalar unit exists for, and it leaves
-// LDS free for the output.
+// for every lane of the grid and known when the library is built, so it is
+// compiled into the instruction stream: no K traffic at all, only the
+// nonzero terms of the contraction are executed, and LDS stays free for the
+// output.
 //
 // Output (template R): with R = 0 every lane stores its own rows with 16-byte
 // vector stores (a wave instruction then touches 64 lines, one 16-byte piece
@@ -28,17 +28,20 @@
 
 namespace fei {
 
-// Block reference tensors, one per (form, dim), in mutable __constant__
-// memory, so the kernels read K at run time rather than folding it into code.
-// The specializations holding the values are generated at build time.
+// Block reference tensors, one per (form, dim), as compile-time constants
+// (the specializations holding the values are generated at build time).
+// Every index is known after unrolling, so the compiler folds K into the
+// code: zero entries drop out and +-1 entries become adds.  The result is
+// bit for bit that of the full multiply-add chain, since fma(0, x, a) = a and
+// fma(+-1, x, a) = a +- x exactly for finite x.
 template <int FORM, int DIM>
-__constant__ KBlockTable<FORM, DIM> c_kblock;
+struct KFold;
 
 template <int FORM, int DIM>
 __device__ __forceinline__ float kval(int i, int j, int mu, int nu)
 {
     using T = Traits<FORM, DIM>;
-    return c_kblock<FORM, DIM>.v[((i * T::NB + j) * DIM + mu) * DIM + nu];
+    return KFold<FORM, DIM>::t.v[((i * T::NB + j) * DIM + mu) * DIM + nu];
 }
 
 // One entry of A from the folded geometric tensor (all indices compile-time
@@ -112,6 +115,7 @@ __device__ __forceinline__ void contract_store(const float (&Au)[Unique<FORM, DI
 // Staged layout: chunk of R rows = CH floats per element, LDS row stride STR
 // floats (16-byte aligned, offset by 4 banks per lane for conflict-free
 // 16-byte accesses).
+
 template <int FORM, int DIM, int R>
 struct Stage {
     static constexpr int N = Traits<FORM, DIM>::N;
@@ -132,87 +136,193 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One workgroup tile (256 elements, 4 waves) of the FP32 forward.  LDS comes
-// from the caller (LDS_BYTES, 16-byte aligned), so one persistent kernel can
-// host the tiles of several forms.
+// One workgroup tile (256 elements, 4 waves) of the FP32 forward, in stages
+// (load -> gather -> compute -> store) so a persistent kernel can overlap
+// them across tiles.  LDS comes from the caller (LDS_BYTES, 16-byte aligned),
+// so one persistent kernel can also host the tiles of several forms.
 template <int FORM, int DIM, typename CT, int R>
 struct FwdFmaTile {
     using T = Traits<FORM, DIM>;
     using S = Stage<FORM, DIM, R>;
-    static constexpr int LDS_BYTES = (R > 0) ? 4 * 64 * S::STR * 4 : 0;
+    using U = Unique<FORM, DIM>;
+    // R == N stages whole matrices, EC elements of the wave at a time, so each
+    // chunk leaves as one contiguous run of EC matrices; R < N stages R rows of
+    // all 64 elements.  The 12 x 12 matrices go 32 at a time (76 KB of LDS per
+    // workgroup instead of 152 KB; measured faster than 64 or 16 at a time).
+    static constexpr bool WHOLE = (R == T::N);
+    static constexpr int EC = WHOLE ? (T::N == 12 ? 32 : 64) : 64;
+    static constexpr int NCH = WHOLE ? 64 / EC : S::NCHUNK;
+    static constexpr int LDS_BYTES = (R > 0) ? 4 * EC * S::STR * 4 : 0;
 
-    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    struct In {             // connectivity of this lane's element
+        int v[DIM + 1];
+    };
+    struct Xv {             // gathered vertex coordinates and coefficients
+        CT x[DIM + 1][DIM];
+        float mu, lam;
+    };
+
+    // Lanes past the last element (and whole tiles past the end) read the
+    // last element and are masked in compute(): the loads carry no branch, so
+    // the compiler need not wait for their data at a join, and a prefetch of
+    // a tile that does not exist stays in bounds.
+    __device__ static int64_t clamp_elem(const FwdParams &p, int64_t blk)
     {
-        const int64_t E = p.m.n_elements;
-        const int64_t e = blk * 256 + threadIdx.x;
-        if constexpr (R == 0) {
-            if (e >= E) return;
+        const int64_t e = blk * 256 + threadIdx.x, E = p.m.n_elements;
+        return e < E ? e : E - 1;
+    }
+
+    __device__ static In load(const FwdParams &p, int64_t blk)
+    {
+        In in;
+        load_conn<DIM>(p.m.conn, clamp_elem(p, blk), in.v);
+        return in;
+    }
+
+    __device__ static Xv gather_xv(const FwdParams &p, int64_t blk, const In &in)
+    {
+        Xv g;
+        gather<DIM>(p.m, in.v, g.x);
+        g.mu = g.lam = 0.f;
+        if constexpr (FORM == ELA1) {
+            const int64_t ec = clamp_elem(p, blk);
+            g.mu = __builtin_nontemporal_load(p.mu + ec);
+            g.lam = __builtin_nontemporal_load(p.lam + ec);
         }
-        const bool valid = e < E;
+        return g;
+    }
+
+    __device__ static void compute(const FwdParams &p, int64_t blk, const Xv &g,
+                                   float (&Au)[U::NU])
+    {
         float Gf[T::G];
         bool flag = false, singular = false;
-        if (valid) {
-            int v[DIM + 1];
-            load_conn<DIM>(p.m.conn, e, v);
-            CT xv[DIM + 1][DIM];
-            gather<DIM>(p.m, v, xv);
-            float mu = 0.f, lam = 0.f;
-            if constexpr (FORM == ELA1) {
-                mu = __builtin_nontemporal_load(p.mu + e);
-                lam = __builtin_nontemporal_load(p.lam + e);
-            }
-            flag = geometry<FORM, DIM>(xv, mu, lam, p.tau2, Gf, singular);
+        if (blk * 256 + threadIdx.x < p.m.n_elements) {
+            flag = geometry<FORM, DIM>(g.x, g.mu, g.lam, p.tau2, Gf, singular);
         } else {
 #pragma unroll
-            for (int g = 0; g < T::G; ++g) Gf[g] = 0.f;
+            for (int k = 0; k < T::G; ++k) Gf[k] = 0.f;
         }
         count_flags(p.counters, flag, singular);
-        float Au[Unique<FORM, DIM>::NU];
         unique_entries<FORM, DIM>(Gf, Au);
+    }
 
+    __device__ static void store(const FwdParams &p, int64_t blk, const float (&Au)[U::NU],
+                                 unsigned char *smem)
+    {
+        const int64_t E = p.m.n_elements;
         if constexpr (R == 0) {
-            contract_store<FORM, DIM>(Au, p.A + e * (int64_t)S::NN);
+            const int64_t e = blk * 256 + threadIdx.x;
+            if (e < E) contract_store<FORM, DIM>(Au, p.A + e * (int64_t)S::NN);
         } else {
             const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-            float *st = reinterpret_cast<float *>(smem) + wave * 64 * S::STR;
-            const int64_t e0 = blk * 256 + wave * 64;
+            float *st = reinterpret_cast<float *>(smem) + wave * EC * S::STR;
+            constexpr int PIECES = EC * S::NV4;     // 16-byte pieces per chunk
 #pragma unroll
-            for (int c = 0; c < S::NCHUNK; ++c) {
-                // this lane's R rows into its LDS row
+            for (int c = 0; c < NCH; ++c) {
+                const int row0 = WHOLE ? 0 : c * S::CH;  // first flat entry of the chunk
+                const int64_t eb = blk * 256 + wave * 64 + (WHOLE ? c * EC : 0);
+                // this lane's chunk rows into its LDS row
+                if (!WHOLE || lane / EC == c) {
+                    float *row = st + (lane % EC) * S::STR;
 #pragma unroll
-                for (int k = 0; k < S::CH; k += 4) {
-                    f32x4_t r;
+                    for (int k = 0; k < S::CH; k += 4) {
+                        f32x4_t r;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int flat = c * S::CH + k + i;
-                        r[i] = Au[sym_index(S::N, flat / S::N, flat % S::N)];
+                        for (int i = 0; i < 4; ++i) {
+                            const int flat = row0 + k + i;
+                            r[i] = Au[sym_index(S::N, flat / S::N, flat % S::N)];
+                        }
+                        *reinterpret_cast<f32x4_t *>(row + k) = r;
                     }
-                    *reinterpret_cast<f32x4_t *>(st + lane * S::STR + k) = r;
                 }
                 wave_sync();
-                // cooperative store of the wave's chunk: piece f -> (element, part)
+                // cooperative store of the chunk: piece f -> (element, part).
+                // A whole-matrix chunk is one contiguous run, piece f at 4 f
+                // floats from its start; a full chunk needs no bounds checks.
+                float *dst = p.A + eb * (int64_t)S::NN + row0;
+                const bool full = WHOLE && eb + EC <= E;
 #pragma unroll
-                for (int k = 0; k < S::NV4; ++k) {
+                for (int k = 0; k < (PIECES + 63) / 64; ++k) {
                     const int f = lane + 64 * k;
                     const int el = f / S::NV4, part = f - el * S::NV4;
-                    const f32x4_t r =
-                        *reinterpret_cast<const f32x4_t *>(st + el * S::STR + 4 * part);
-                    if (e0 + el < E)
-                        store_out(reinterpret_cast<f32x4_t *>(p.A + (e0 + el) * (int64_t)S::NN +
-                                                              c * S::CH + 4 * part), r);
+                    if (PIECES % 64 == 0 || f < PIECES) {
+                        const f32x4_t r =
+                            *reinterpret_cast<const f32x4_t *>(st + el * S::STR + 4 * part);
+                        if (full)
+                            store_out(reinterpret_cast<f32x4_t *>(dst + 4 * f), r);
+                        else if (eb + el < E)
+                            store_out(reinterpret_cast<f32x4_t *>(dst + el * S::NN + 4 * part), r);
+                    }
+#ifdef FEI_STORE_SUB
+                    if ((k + 1) % FEI_STORE_SUB == 0) __builtin_amdgcn_sched_barrier(0);
+#endif
                 }
                 wave_sync();
             }
         }
     }
+
+    // The whole tile in order (batch kernels).
+    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    {
+        const Xv g = gather_xv(p, blk, load(p, blk));
+        float Au[U::NU];
+        compute(p, blk, g, Au);
+        store(p, blk, Au, smem);
+    }
 };
 
+// Tiles of a persistent workgroup: the tiles are split into contiguous
+// ranges, one per XCD that has workgroups (workgroups are dispatched
+// round-robin over the 8 XCDs), and the workgroups of an XCD stride through
+// its range.  With G < 8 workgroups only XCDs 0..G-1 get a range.
+struct PersistentTiles {
+    int64_t begin, end, stride;
+    __device__ PersistentTiles(int64_t n_tiles)
+    {
+        const int64_t G = gridDim.x, b = blockIdx.x;
+        const int64_t X = G < 8 ? G : 8;
+        const int64_t x = b % 8, i = b / 8;
+        const int64_t cnt = G / 8 + (x < G % 8 ? 1 : 0);
+        const int64_t r0 = x * n_tiles / X, r1 = (x + 1) * n_tiles / X;
+        begin = r0 + i;
+        end = r1;
+        stride = cnt;
+    }
+};
+
+// Persistent, software-pipelined FP32 forward.  Vector-memory loads and
+// stores complete in issue order for s_waitcnt, so waiting on a load issued
+// after a tile's stores would wait for those stores.  Each iteration
+// therefore issues the next tile's coordinate gather and the connectivity of
+// the tile after it BEFORE storing the current tile, and only then waits for
+// them: the stores drain while the next tile is computed.  Only the
+// connectivity is carried across iterations, and the old copy is dead once
+// gathered, so the two share registers.
 template <int FORM, int DIM, typename CT, int R>
-__global__ __launch_bounds__(256) void fwd_fma_kernel(FwdParams p)
+__global__ __launch_bounds__(256) void fwd_fma_kernel(FwdParams p, int64_t n_tiles)
 {
     using Tile = FwdFmaTile<FORM, DIM, CT, R>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES > 0 ? Tile::LDS_BYTES : 16];
-    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
+    const PersistentTiles pt(n_tiles);
+    int64_t t = pt.begin;
+    if (t >= pt.end) return;
+    float Au[Unique<FORM, DIM>::NU];
+    {
+        const typename Tile::Xv g = Tile::gather_xv(p, t, Tile::load(p, t));
+        Tile::compute(p, t, g, Au);
+    }
+    typename Tile::In conn = Tile::load(p, t + pt.stride);
+    for (;;) {
+        const int64_t tn = t + pt.stride;
+        const typename Tile::Xv g = Tile::gather_xv(p, tn, conn);
+        conn = Tile::load(p, tn + pt.stride);
+        Tile::store(p, t, Au, smem);
+        if (tn >= pt.end) break;
+        Tile::compute(p, tn, g, Au);
+        t = tn;
+    }
 }
 
 }  // namespace fei

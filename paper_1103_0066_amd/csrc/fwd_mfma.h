@@ -278,25 +278,6 @@ struct MfmaTile {
     }
 };
 
-// Tiles of a persistent workgroup: the tiles are split into contiguous
-// ranges, one per XCD that has workgroups (workgroups are dispatched
-// round-robin over the 8 XCDs), and the workgroups of an XCD stride through
-// its range.  With G < 8 workgroups only XCDs 0..G-1 get a range.
-struct PersistentTiles {
-    int64_t begin, end, stride;
-    __device__ PersistentTiles(int64_t n_tiles)
-    {
-        const int64_t G = gridDim.x, b = blockIdx.x;
-        const int64_t X = G < 8 ? G : 8;
-        const int64_t x = b % 8, i = b / 8;
-        const int64_t cnt = G / 8 + (x < G % 8 ? 1 : 0);
-        const int64_t r0 = x * n_tiles / X, r1 = (x + 1) * n_tiles / X;
-        begin = r0 + i;
-        end = r1;
-        stride = cnt;
-    }
-};
-
 template <int FORM, int DIM, typename CT, int PREC, bool DIRECT>
 __global__ __launch_bounds__(256) void fwd_mfma_kernel(FwdParams p, int64_t n_tiles)
 {

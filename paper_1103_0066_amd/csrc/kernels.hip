@@ -1,6 +1,7 @@
 // All device code of libfei: kernel instantiations and the launcher tables
 // the host layer dispatches through.  One translation unit, so the
-// __constant__ reference tables exist once per device module.
+// device-global reference tables (K fragments, sparse K) exist once per
+// device module.
 #include <type_traits>
 
 #include "adjoint.h"
@@ -19,11 +20,15 @@ constexpr int kBlock = 256;
 
 inline unsigned grid_for(int64_t E) { return unsigned((E + kBlock - 1) / kBlock); }
 
+template <typename K>
+int persistent_grid(K kernel, int64_t n_tiles);
+
 template <int F, int D, typename CT, int R>
 hipError_t launch_fwd_fma(const FwdParams &p, hipStream_t s)
 {
-    hipLaunchKernelGGL((fwd_fma_kernel<F, D, CT, R>), dim3(grid_for(p.m.n_elements)),
-                       dim3(kBlock), 0, s, p);
+    const int64_t n_tiles = (p.m.n_elements + kBlock - 1) / kBlock;
+    auto k = fwd_fma_kernel<F, D, CT, R>;
+    hipLaunchKernelGGL(k, dim3(persistent_grid(k, n_tiles)), dim3(kBlock), 0, s, p, n_tiles);
     return hipGetLastError();
 }
 
@@ -71,14 +76,13 @@ constexpr bool rows_ok()
 }
 
 // Tuned defaults of the staging rows (measured on MI355X).  Forward: whole
-// matrices, except 3D elasticity where 4-row chunks keep LDS at 53 KB per
-// workgroup (3 workgroups per CU) and beat whole 151 KB matrices; adjoint: a
-// third of the matrix or less, leaving LDS room for the vertex-merge table.
+// matrices (each staged chunk leaves as one contiguous run; row chunks leave
+// strided runs and measured up to 2.5x slower); adjoint: a third of the
+// matrix or less, leaving LDS room for the vertex-merge table.
 template <int F, int D>
 constexpr int default_rows()
 {
     constexpr int N = Traits<F, D>::N;
-    if constexpr (N == 12) return 4;
     return (N * N) % 4 == 0 ? N : 0;
 }
 

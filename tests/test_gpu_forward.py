@@ -93,7 +93,7 @@ def test_forward_staging_modes(case, precision, rows):
     assert np.array_equal(A.view(np.uint32), A0.view(np.uint32))
 
 
-@pytest.mark.parametrize("precision,rows", [("fp32", 0), ("fp32", -1), ("fp16x2", 0),
+@pytest.mark.parametrize("precision,rows", [("fp32", 0), ("fp32", -1), ("fp32", 4), ("fp16x2", 0),
                                             ("fp16x2", -1), ("bf16x3", 0)])
 def test_every_tile_count_is_covered(precision, rows):
     """1 to 10 workgroup tiles (persistent kernels split tiles over the XCDs that
