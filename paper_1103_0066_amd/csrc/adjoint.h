@@ -264,134 +264,302 @@ struct AdjTile {
     static constexpr int NN = S::NN;
     static constexpr int GP = ((T::G + 1) / 2) * 2;
     static constexpr int SW = (R > 0) ? ((64 * S::STR > NN) ? 64 * S::STR : NN) : ((NN + 3) / 4) * 4;
-    // LDS: dA staging | FP64 fold of a flagged element | vertex-merge keys | values
+    // Flagged elements of a wave whose dA is kept in LDS while it streams past
+    // (further flagged elements of the same wave reload theirs from memory).
+    static constexpr int NSTASH = (R > 0 && sizeof(CT) == 4) ? 2 : 0;
+    // LDS: dA staging | FP64 fold of a flagged element | vertex-merge keys |
+    // values | stashed dA of flagged elements
     static constexpr int OFF_U64 = 4 * SW * 4;
     static constexpr int OFF_KEY = OFF_U64 + 4 * GP * 8;
     static constexpr int OFF_VAL = OFF_KEY + 4 * kHashSlots * 4;
-    static constexpr int LDS_BYTES = OFF_VAL + 4 * kHashSlots * DIM * 4;
+    static constexpr int OFF_STASH = OFF_VAL + 4 * kHashSlots * DIM * 4;
+    static constexpr int LDS_BYTES = OFF_STASH + 4 * NSTASH * NN * 4;
 
-    __device__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem)
+    struct Lds {
+        float *st;       // staging rows (SW floats)
+        double *u64;     // FP64 fold (GP doubles)
+        int *key;        // vertex-merge table
+        float *val;
+        float *stash;    // NSTASH whole dA matrices
+    };
+    __device__ static Lds lds(unsigned char *smem)
     {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        const int64_t E = p.m.n_elements;
-        const int64_t e0 = blk * 256 + wave * 64;
-        const int64_t e = e0 + lane;
-        const bool valid = e < E;
-        float *st = reinterpret_cast<float *>(smem) + wave * SW;
-        double *u64 = reinterpret_cast<double *>(smem + OFF_U64) + wave * GP;
-        int *key = reinterpret_cast<int *>(smem + OFF_KEY) + wave * kHashSlots;
-        float *val = reinterpret_cast<float *>(smem + OFF_VAL) + wave * kHashSlots * DIM;
+        const int wave = wave_id();
+        return {reinterpret_cast<float *>(smem) + wave * SW,
+                reinterpret_cast<double *>(smem + OFF_U64) + wave * GP,
+                reinterpret_cast<int *>(smem + OFF_KEY) + wave * kHashSlots,
+                reinterpret_cast<float *>(smem + OFF_VAL) + wave * kHashSlots * DIM,
+                reinterpret_cast<float *>(smem + OFF_STASH) + wave * NSTASH * NN};
+    }
 
-        int v[DIM + 1] = {};
-        CT xv[DIM + 1][DIM] = {};
-        float mu = 0.f, lam = 0.f;
-        if (valid) {
-            load_conn<DIM>(p.m.conn, e, v);
-            gather<DIM>(p.m, v, xv);
-            if constexpr (FORM == ELA1) {
-                mu = __builtin_nontemporal_load(p.mu + e);
-                lam = __builtin_nontemporal_load(p.lam + e);
-            }
+    struct In {          // connectivity of this lane's element
+        int v[DIM + 1];
+    };
+    struct Xv {          // gathered vertex coordinates and coefficients
+        CT x[DIM + 1][DIM];
+        float mu, lam;
+    };
+    struct Chunk {       // the wave's 16-byte dA pieces of one staged chunk
+        f32x4_t r[(R > 0) ? S::NV4 : 1];
+    };
+
+    // Loads of lanes past the last element (and of tiles past the end) read
+    // the last element; their results are never used.  No branch around a
+    // load, so prefetched data is waited for only where it is consumed.
+    __device__ static int64_t clamp(const AdjParams &p, int64_t e)
+    {
+        return e < p.m.n_elements ? e : p.m.n_elements - 1;
+    }
+
+    __device__ static In load(const AdjParams &p, int64_t blk)
+    {
+        In in;
+        load_conn<DIM>(p.m.conn, clamp(p, blk * 256 + threadIdx.x), in.v);
+        return in;
+    }
+
+    __device__ static Xv gather_xv(const AdjParams &p, int64_t blk, const In &in)
+    {
+        Xv g;
+        gather<DIM>(p.m, in.v, g.x);
+        g.mu = g.lam = 0.f;
+        if constexpr (FORM == ELA1) {
+            const int64_t e = clamp(p, blk * 256 + threadIdx.x);
+            g.mu = __builtin_nontemporal_load(p.mu + e);
+            g.lam = __builtin_nontemporal_load(p.lam + e);
         }
+        return g;
+    }
 
-        // U = folded K^T applied to dA
-        AccT U[T::G];
-#pragma unroll
-        for (int g = 0; g < T::G; ++g) U[g] = AccT(0);
-        if constexpr (R > 0) {
-#pragma unroll
-            for (int c = 0; c < S::NCHUNK; ++c) {
-#pragma unroll
-                for (int k = 0; k < S::NV4; ++k) {
-                    const int f = lane + 64 * k;
-                    const int el = f / S::NV4, part = f - el * S::NV4;
-                    f32x4_t r = {0.f, 0.f, 0.f, 0.f};
-                    if (e0 + el < E)
-                        r = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(
-                            p.dA + (e0 + el) * (int64_t)NN + c * S::CH + 4 * part));
-                    *reinterpret_cast<f32x4_t *>(st + el * S::STR + 4 * part) = r;
-                }
-                wave_sync();
-#pragma unroll
-                for (int k = 0; k < S::CH; k += 4) {
-                    const f32x4_t w = *reinterpret_cast<const f32x4_t *>(st + lane * S::STR + k);
-                    const float r[4] = {w[0], w[1], w[2], w[3]};
-                    fold_piece<FORM, DIM, AccT>(U, c * S::CH + k, r, 4);
-                }
-                wave_sync();
-            }
-        } else if (valid) {
-            const float *__restrict__ dAe = p.dA + e * (int64_t)NN;
-#pragma unroll
-            for (int k = 0; k < NN; k += 4) {
-                float r[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (k + i < NN) r[i] = __builtin_nontemporal_load(dAe + k + i);
-                fold_piece<FORM, DIM, AccT>(U, k, r, NN - k < 4 ? NN - k : 4);
-            }
-        }
-
-        float Jbar[DIM][DIM], mubar = 0.f, lambar = 0.f;
-        bool flag = false, singular = false;
+    // Quality test ahead of the fold, so flagged elements can be stashed.
+    __device__ static bool flagged(const AdjParams &p, int64_t blk, const Xv &g)
+    {
         if constexpr (sizeof(CT) == 8) {
-            double J[DIM][DIM], adj[DIM][DIM];
-            jacobian<DIM>(xv, J);
-            const double det = adjugate(J, adj);
-            singular = valid && det == 0.0;
-            adjoint_chain<FORM, DIM>(adj, det, mu, lam, SRegs<FORM, DIM, AccT>{U}, Jbar, mubar, lambar);
+            return false;
         } else {
             float J[DIM][DIM], adj[DIM][DIM];
-            jacobian<DIM>(xv, J);
+            jacobian<DIM>(g.x, J);
             const float det = adjugate(J, adj);
-            flag = valid && needs_fp64<DIM>(J, adj, det, p.tau2);
-            if (!flag)
-                adjoint_chain<FORM, DIM>(adj, det, mu, lam, SRegs<FORM, DIM, AccT>{U}, Jbar, mubar,
-                                         lambar);
+            return blk * 256 + threadIdx.x < p.m.n_elements && needs_fp64<DIM>(J, adj, det, p.tau2);
+        }
+    }
+
+    // Chunk c of the wave's dA: consecutive lanes on consecutive 16-byte pieces.
+    __device__ static Chunk load_chunk(const AdjParams &p, int64_t blk, int c)
+    {
+        Chunk ch;
+        if constexpr (R > 0) {
+            const int lane = threadIdx.x & 63;
+            const int64_t e0 = blk * 256 + wave_id() * 64;
+#pragma unroll
+            for (int k = 0; k < S::NV4; ++k) {
+                const int f = lane + 64 * k;
+                const int el = f / S::NV4, part = f - el * S::NV4;
+                ch.r[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(
+                    p.dA + clamp(p, e0 + el) * (int64_t)NN + c * S::CH + 4 * part));
+            }
+        }
+        return ch;
+    }
+
+    // Stage chunk c through the wave's LDS rows, fold this lane's rows into U,
+    // and copy the rows of (up to NSTASH) flagged elements into the stash.
+    __device__ static void fold_chunk(const Lds &L, int c, const Chunk &ch, unsigned long long fm,
+                                      AccT (&U)[T::G])
+    {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int k = 0; k < S::NV4; ++k) {
+            const int f = lane + 64 * k;
+            const int el = f / S::NV4, part = f - el * S::NV4;
+            *reinterpret_cast<f32x4_t *>(L.st + el * S::STR + 4 * part) = ch.r[k];
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < S::CH; k += 4) {
+            const f32x4_t w = *reinterpret_cast<const f32x4_t *>(L.st + lane * S::STR + k);
+            const float r[4] = {w[0], w[1], w[2], w[3]};
+            fold_piece<FORM, DIM, AccT>(U, c * S::CH + k, r, 4);
+        }
+#pragma unroll
+        for (int s = 0; s < NSTASH; ++s) {
+            if (!fm) break;
+            const int el = __ffsll(fm) - 1;
+            fm &= fm - 1;
+            for (int k = lane; k < S::CH; k += 64)
+                L.stash[s * NN + c * S::CH + k] = L.st[el * S::STR + k];
+        }
+        wave_sync();
+    }
+
+    // R == 0: every lane folds its own dA directly.
+    __device__ static void fold_direct(const AdjParams &p, int64_t blk, AccT (&U)[T::G])
+    {
+        const float *__restrict__ dAe = p.dA + clamp(p, blk * 256 + threadIdx.x) * (int64_t)NN;
+#pragma unroll
+        for (int k = 0; k < NN; k += 4) {
+            float r[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (k + i < NN) r[i] = __builtin_nontemporal_load(dAe + k + i);
+            fold_piece<FORM, DIM, AccT>(U, k, r, NN - k < 4 ? NN - k : 4);
+        }
+    }
+
+    // Per-lane results of the reverse pass of one tile.
+    struct Rev {
+        float Jbar[DIM][DIM];
+        float mubar, lambar;
+        bool flag, singular;
+    };
+
+    // Reverse geometry of a tile whose U is folded.  fm: the wave's flagged
+    // lanes, the first NSTASH of them with their dA in the stash.
+    __device__ static Rev reverse(const AdjParams &p, int64_t blk, const Xv &g,
+                                  const AccT (&U)[T::G], unsigned long long fm, const Lds &L)
+    {
+        const int lane = threadIdx.x & 63;
+        const int64_t e0 = blk * 256 + wave_id() * 64;
+        Rev o;
+        o.mubar = o.lambar = 0.f;
+        o.singular = false;
+        o.flag = (fm >> lane) & 1;
+        if constexpr (sizeof(CT) == 8) {
+            double J[DIM][DIM], adj[DIM][DIM];
+            jacobian<DIM>(g.x, J);
+            const double det = adjugate(J, adj);
+            o.singular = e0 + lane < p.m.n_elements && det == 0.0;
+            adjoint_chain<FORM, DIM>(adj, det, g.mu, g.lam, SRegs<FORM, DIM, AccT>{U}, o.Jbar,
+                                     o.mubar, o.lambar);
+        } else {
+            if (!o.flag) {
+                float J[DIM][DIM], adj[DIM][DIM];
+                jacobian<DIM>(g.x, J);
+                const float det = adjugate(J, adj);
+                adjoint_chain<FORM, DIM>(adj, det, g.mu, g.lam, SRegs<FORM, DIM, AccT>{U}, o.Jbar,
+                                         o.mubar, o.lambar);
+            }
             // flagged elements, one at a time: FP64 fold by the wave, FP64 chain by the owner
-            unsigned long long fm = __ballot(flag);
+            int slot = 0;
             while (fm) {
-                const int L = __ffsll(fm) - 1;
+                const int Lf = __ffsll(fm) - 1;
                 fm &= fm - 1;
-                const int64_t eL = e0 + L;
-                for (int k = lane; k < NN; k += 64)
-                    st[k] = __builtin_nontemporal_load(p.dA + eL * (int64_t)NN + k);
+                const float *src = L.stash + slot * NN;
+                if (slot >= NSTASH) {
+                    for (int k = lane; k < NN; k += 64)
+                        L.st[k] = __builtin_nontemporal_load(p.dA + (e0 + Lf) * (int64_t)NN + k);
+                    src = L.st;
+                }
+                ++slot;
                 wave_sync();
                 if (lane < T::G) {
                     constexpr int NZ = KSparseShape<FORM, DIM>::NNZ;
                     const KSparse<FORM, DIM> &ks = g_ksparse<FORM, DIM>;
                     double u = 0.0;
                     for (int t = 0; t < NZ; ++t)
-                        u += double(ks.coef[lane][t]) * double(st[ks.ij[lane][t]]);
-                    u64[lane] = u;
+                        u += double(ks.coef[lane][t]) * double(src[ks.ij[lane][t]]);
+                    L.u64[lane] = u;
                 }
                 wave_sync();
-                if (lane == L) {
+                if (lane == Lf) {
                     double Jd[DIM][DIM], adjd[DIM][DIM];
-                    jacobian<DIM>(xv, Jd);
+                    jacobian<DIM>(g.x, Jd);
                     const double detd = adjugate(Jd, adjd);
-                    singular = (detd == 0.0);
-                    adjoint_chain<FORM, DIM>(adjd, detd, mu, lam, SLds{u64, T::GD}, Jbar,
-                                             mubar, lambar);
+                    o.singular = (detd == 0.0);
+                    adjoint_chain<FORM, DIM>(adjd, detd, g.mu, g.lam, SLds{L.u64, T::GD}, o.Jbar,
+                                             o.mubar, o.lambar);
                 }
                 wave_sync();
             }
         }
-        count_flags(p.counters, flag, singular);
+        return o;
+    }
+
+    // Counters, coefficient gradients and the vertex scatter of a tile.
+    __device__ static void emit(const AdjParams &p, int64_t blk, const In &in, const Rev &o,
+                                const Lds &L)
+    {
+        const int lane = threadIdx.x & 63;
+        const int64_t e = blk * 256 + threadIdx.x;
+        const bool valid = e < p.m.n_elements;
+        count_flags(p.counters, o.flag, o.singular);
         if constexpr (FORM == ELA1) {
-            if (valid && p.dmu) p.dmu[e] = mubar;
-            if (valid && p.dlam) p.dlam[e] = lambar;
+            if (valid && p.dmu) p.dmu[e] = o.mubar;
+            if (valid && p.dlam) p.dlam[e] = o.lambar;
         }
-        scatter_vertices<DIM>(p, v, Jbar, valid, key, val, lane);
+        scatter_vertices<DIM>(p, in.v, o.Jbar, valid, L.key, L.val, lane);
+    }
+
+    // The whole tile in order (batch kernels).
+    __device__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem)
+    {
+        const Lds L = lds(smem);
+        const In in = load(p, blk);
+        const Xv g = gather_xv(p, blk, in);
+        const unsigned long long fm = __ballot(flagged(p, blk, g));
+        AccT U[T::G];
+#pragma unroll
+        for (int k = 0; k < T::G; ++k) U[k] = AccT(0);
+        if constexpr (R > 0) {
+#pragma unroll
+            for (int c = 0; c < S::NCHUNK; ++c) fold_chunk(L, c, load_chunk(p, blk, c), fm, U);
+        } else {
+            fold_direct(p, blk, U);
+        }
+        emit(p, blk, in, reverse(p, blk, g, U, fm, L), L);
     }
 };
 
+// Persistent, software-pipelined adjoint (tiles split over the XCDs as in
+// the forward).  Loads run one step ahead of their use: chunk c + 1 of a tile
+// is in flight while chunk c is staged and folded; the next tile's
+// coordinates are gathered during the last chunk, and its chunk 0 is issued
+// after the reverse pass, before this tile's atomics.  Vector-memory
+// operations complete in issue order, so every prefetch is issued before the
+// stores and atomics of the step it overlaps.
 template <int FORM, int DIM, typename CT, int R>
-__global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p)
+__global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p, int64_t n_tiles)
 {
     using Tile = AdjTile<FORM, DIM, CT, R>;
+    using AccT = typename Tile::AccT;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
-    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
+    const PersistentTiles pt(n_tiles);
+    if constexpr (R == 0) {
+        for (int64_t t = pt.begin; t < pt.end; t += pt.stride) Tile::run(p, t, smem);
+    } else {
+        constexpr int NCH = Stage<FORM, DIM, R>::NCHUNK;
+        const typename Tile::Lds L = Tile::lds(smem);
+        int64_t t = pt.begin;
+        if (t >= pt.end) return;
+        typename Tile::In cur = Tile::load(p, t);
+        typename Tile::Xv g = Tile::gather_xv(p, t, cur);
+        typename Tile::In nxt = Tile::load(p, t + pt.stride);
+        typename Tile::Chunk ch = Tile::load_chunk(p, t, 0);
+        for (;;) {
+            const int64_t tn = t + pt.stride;
+            const unsigned long long fm = __ballot(Tile::flagged(p, t, g));
+            AccT U[Traits<FORM, DIM>::G];
+#pragma unroll
+            for (int k = 0; k < Traits<FORM, DIM>::G; ++k) U[k] = AccT(0);
+            typename Tile::Xv gn;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                typename Tile::Chunk nx;
+                if (c + 1 < NCH) nx = Tile::load_chunk(p, t, c + 1);
+                if (c + 1 == NCH) gn = Tile::gather_xv(p, tn, nxt);
+                Tile::fold_chunk(L, c, ch, fm, U);
+                if (c + 1 < NCH) ch = nx;
+            }
+            const typename Tile::Rev o = Tile::reverse(p, t, g, U, fm, L);
+            ch = Tile::load_chunk(p, tn, 0);
+            Tile::emit(p, t, cur, o, L);
+            if (tn >= pt.end) break;
+            cur = nxt;
+            nxt = Tile::load(p, tn + pt.stride);
+            g = gn;
+            t = tn;
+        }
+    }
 }
 
 }  // namespace fei

@@ -166,38 +166,41 @@ struct FwdFmaTile {
     // last element and are masked in compute(): the loads carry no branch, so
     // the compiler need not wait for their data at a join, and a prefetch of
     // a tile that does not exist stays in bounds.
-    __device__ static int64_t clamp_elem(const FwdParams &p, int64_t blk)
+    //
+    // Every stage takes e0, the first element of the wave's 64; lane l owns
+    // element e0 + l.
+    __device__ static int64_t clamp_elem(const FwdParams &p, int64_t e0)
     {
-        const int64_t e = blk * 256 + threadIdx.x, E = p.m.n_elements;
+        const int64_t e = e0 + (threadIdx.x & 63), E = p.m.n_elements;
         return e < E ? e : E - 1;
     }
 
-    __device__ static In load(const FwdParams &p, int64_t blk)
+    __device__ static In load(const FwdParams &p, int64_t e0)
     {
         In in;
-        load_conn<DIM>(p.m.conn, clamp_elem(p, blk), in.v);
+        load_conn<DIM>(p.m.conn, clamp_elem(p, e0), in.v);
         return in;
     }
 
-    __device__ static Xv gather_xv(const FwdParams &p, int64_t blk, const In &in)
+    __device__ static Xv gather_xv(const FwdParams &p, int64_t e0, const In &in)
     {
         Xv g;
         gather<DIM>(p.m, in.v, g.x);
         g.mu = g.lam = 0.f;
         if constexpr (FORM == ELA1) {
-            const int64_t ec = clamp_elem(p, blk);
+            const int64_t ec = clamp_elem(p, e0);
             g.mu = __builtin_nontemporal_load(p.mu + ec);
             g.lam = __builtin_nontemporal_load(p.lam + ec);
         }
         return g;
     }
 
-    __device__ static void compute(const FwdParams &p, int64_t blk, const Xv &g,
+    __device__ static void compute(const FwdParams &p, int64_t e0, const Xv &g,
                                    float (&Au)[U::NU])
     {
         float Gf[T::G];
         bool flag = false, singular = false;
-        if (blk * 256 + threadIdx.x < p.m.n_elements) {
+        if (e0 + (threadIdx.x & 63) < p.m.n_elements) {
             flag = geometry<FORM, DIM>(g.x, g.mu, g.lam, p.tau2, Gf, singular);
         } else {
 #pragma unroll
@@ -207,21 +210,21 @@ struct FwdFmaTile {
         unique_entries<FORM, DIM>(Gf, Au);
     }
 
-    __device__ static void store(const FwdParams &p, int64_t blk, const float (&Au)[U::NU],
+    __device__ static void store(const FwdParams &p, int64_t e0, const float (&Au)[U::NU],
                                  unsigned char *smem)
     {
         const int64_t E = p.m.n_elements;
         if constexpr (R == 0) {
-            const int64_t e = blk * 256 + threadIdx.x;
+            const int64_t e = e0 + (threadIdx.x & 63);
             if (e < E) contract_store<FORM, DIM>(Au, p.A + e * (int64_t)S::NN);
         } else {
-            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            const int lane = threadIdx.x & 63, wave = wave_id();
             float *st = reinterpret_cast<float *>(smem) + wave * EC * S::STR;
             constexpr int PIECES = EC * S::NV4;     // 16-byte pieces per chunk
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int row0 = WHOLE ? 0 : c * S::CH;  // first flat entry of the chunk
-                const int64_t eb = blk * 256 + wave * 64 + (WHOLE ? c * EC : 0);
+                const int64_t eb = e0 + (WHOLE ? c * EC : 0);
                 // this lane's chunk rows into its LDS row
                 if (!WHOLE || lane / EC == c) {
                     float *row = st + (lane % EC) * S::STR;
@@ -239,24 +242,36 @@ struct FwdFmaTile {
                 wave_sync();
                 // cooperative store of the chunk: piece f -> (element, part).
                 // A whole-matrix chunk is one contiguous run, piece f at 4 f
-                // floats from its start; a full chunk needs no bounds checks.
+                // floats from its start; a full chunk (wave-uniform test) reads
+                // all its pieces first, then stores them without checks.
                 float *dst = p.A + eb * (int64_t)S::NN + row0;
-                const bool full = WHOLE && eb + EC <= E;
+                constexpr int NP = (PIECES + 63) / 64;
+                if (PIECES % 64 == 0 && eb + EC <= E) {
+                    f32x4_t r[NP];
 #pragma unroll
-                for (int k = 0; k < (PIECES + 63) / 64; ++k) {
-                    const int f = lane + 64 * k;
-                    const int el = f / S::NV4, part = f - el * S::NV4;
-                    if (PIECES % 64 == 0 || f < PIECES) {
-                        const f32x4_t r =
-                            *reinterpret_cast<const f32x4_t *>(st + el * S::STR + 4 * part);
-                        if (full)
-                            store_out(reinterpret_cast<f32x4_t *>(dst + 4 * f), r);
-                        else if (eb + el < E)
-                            store_out(reinterpret_cast<f32x4_t *>(dst + el * S::NN + 4 * part), r);
+                    for (int k = 0; k < NP; ++k) {
+                        const int f = lane + 64 * k;
+                        const int el = f / S::NV4, part = f - el * S::NV4;
+                        r[k] = *reinterpret_cast<const f32x4_t *>(st + el * S::STR + 4 * part);
                     }
-#ifdef FEI_STORE_SUB
-                    if ((k + 1) % FEI_STORE_SUB == 0) __builtin_amdgcn_sched_barrier(0);
-#endif
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        const int f = lane + 64 * k;
+                        const int el = f / S::NV4, part = f - el * S::NV4;
+                        store_out(reinterpret_cast<f32x4_t *>(
+                                      dst + (WHOLE ? 4 * f : el * S::NN + 4 * part)), r[k]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        const int f = lane + 64 * k;
+                        const int el = f / S::NV4, part = f - el * S::NV4;
+                        if ((PIECES % 64 == 0 || f < PIECES) && eb + el < E) {
+                            const f32x4_t r =
+                                *reinterpret_cast<const f32x4_t *>(st + el * S::STR + 4 * part);
+                            store_out(reinterpret_cast<f32x4_t *>(dst + el * S::NN + 4 * part), r);
+                        }
+                    }
                 }
                 wave_sync();
             }
@@ -266,10 +281,11 @@ struct FwdFmaTile {
     // The whole tile in order (batch kernels).
     __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
     {
-        const Xv g = gather_xv(p, blk, load(p, blk));
+        const int64_t e0 = blk * 256 + wave_id() * 64;
+        const Xv g = gather_xv(p, e0, load(p, e0));
         float Au[U::NU];
-        compute(p, blk, g, Au);
-        store(p, blk, Au, smem);
+        compute(p, e0, g, Au);
+        store(p, e0, Au, smem);
     }
 };
 
@@ -292,37 +308,95 @@ struct PersistentTiles {
     }
 };
 
-// Persistent, software-pipelined FP32 forward.  Vector-memory loads and
-// stores complete in issue order for s_waitcnt, so waiting on a load issued
-// after a tile's stores would wait for those stores.  Each iteration
-// therefore issues the next tile's coordinate gather and the connectivity of
-// the tile after it BEFORE storing the current tile, and only then waits for
-// them: the stores drain while the next tile is computed.  Only the
-// connectivity is carried across iterations, and the old copy is dead once
-// gathered, so the two share registers.
+// Wave tiles (64 elements) of a persistent grid: one contiguous range per
+// XCD that has workgroups (workgroups are dispatched round-robin over the 8
+// XCDs); the waves of an XCD take every (4 x workgroups)-th tile of its range.
+struct WaveTiles {
+    int64_t next_t, end, stride;
+    __device__ WaveTiles(int64_t n_tiles)
+    {
+        const int64_t G = gridDim.x, b = blockIdx.x;
+        const int64_t X = G < 8 ? G : 8;
+        const int64_t x = b % 8, i = b / 8;
+        const int64_t cnt = G / 8 + (x < G % 8 ? 1 : 0);
+        end = (x + 1) * n_tiles / X;
+        next_t = x * n_tiles / X + i * 4 + wave_id();
+        stride = 4 * cnt;
+    }
+    // next tile of this wave; >= end once the range is exhausted
+    __device__ int64_t pop()
+    {
+        const int64_t t = next_t;
+        next_t += stride;
+        return t;
+    }
+    __device__ void done() {}
+};
+
+#ifdef FEI_DYN
+__device__ unsigned long long g_dyn[2];
+struct DynTiles {
+    int64_t end;
+    __device__ DynTiles(int64_t n_tiles) : end(n_tiles) {}
+    __device__ int64_t pop()
+    {
+        unsigned long long v = 0;
+        if ((threadIdx.x & 63) == 0) v = atomicAdd(&g_dyn[0], 1ull);
+        return int64_t(__builtin_amdgcn_readfirstlane(unsigned(v)));
+    }
+    __device__ void done()
+    {
+        if ((threadIdx.x & 63) == 0) {
+            const unsigned long long d = atomicAdd(&g_dyn[1], 1ull);
+            if (d + 1 == 4ull * gridDim.x) {
+                atomicExch(&g_dyn[0], 0ull);
+                atomicExch(&g_dyn[1], 0ull);
+            }
+        }
+    }
+};
+#endif
+
+// Persistent, software-pipelined FP32 forward over wave tiles.  Vector-memory
+// loads and stores complete in issue order for s_waitcnt, so waiting on a
+// load issued after a tile's stores would wait for those stores.  Each
+// iteration therefore issues the next tile's coordinate gather and the
+// connectivity of the tile after it BEFORE storing the current tile, and only
+// then waits for them: the stores drain while the next tile is computed.
+// Only the connectivity is carried across iterations, and the old copy is
+// dead once gathered, so the two share registers.
 template <int FORM, int DIM, typename CT, int R>
 __global__ __launch_bounds__(256) void fwd_fma_kernel(FwdParams p, int64_t n_tiles)
 {
     using Tile = FwdFmaTile<FORM, DIM, CT, R>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES > 0 ? Tile::LDS_BYTES : 16];
-    const PersistentTiles pt(n_tiles);
-    int64_t t = pt.begin;
-    if (t >= pt.end) return;
-    float Au[Unique<FORM, DIM>::NU];
-    {
-        const typename Tile::Xv g = Tile::gather_xv(p, t, Tile::load(p, t));
-        Tile::compute(p, t, g, Au);
+#ifdef FEI_DYN
+    DynTiles ws(n_tiles);
+#else
+    WaveTiles ws(n_tiles);
+#endif
+    int64_t t = ws.pop();
+    if (t < ws.end) {
+        float Au[Unique<FORM, DIM>::NU];
+        {
+            const typename Tile::Xv g = Tile::gather_xv(p, t * 64, Tile::load(p, t * 64));
+            Tile::compute(p, t * 64, g, Au);
+        }
+        int64_t tn = ws.pop();
+        typename Tile::In conn = Tile::load(p, tn * 64);
+        for (;;) {
+            const typename Tile::Xv g = Tile::gather_xv(p, tn * 64, conn);
+            const bool more = tn < ws.end;
+            const int64_t tnn = more ? ws.pop() : tn;
+            conn = Tile::load(p, tnn * 64);
+            Tile::store(p, t * 64, Au, smem);
+            if (!more) break;
+            Tile::compute(p, tn * 64, g, Au);
+            t = tn;
+            tn = tnn;
+        }
     }
-    typename Tile::In conn = Tile::load(p, t + pt.stride);
-    for (;;) {
-        const int64_t tn = t + pt.stride;
-        const typename Tile::Xv g = Tile::gather_xv(p, tn, conn);
-        conn = Tile::load(p, tn + pt.stride);
-        Tile::store(p, t, Au, smem);
-        if (tn >= pt.end) break;
-        Tile::compute(p, tn, g, Au);
-        t = tn;
-    }
+    ws.done();
 }
 
 }  // namespace fei

@@ -195,6 +195,14 @@ __device__ __forceinline__ void count_flags(int32_t *counters, bool flag, bool s
     }
 }
 
+// Index of this lane's wave in the workgroup, as a wave-uniform value (the
+// compiler cannot see that threadIdx.x >> 6 is uniform; said explicitly,
+// per-wave bases stay in SGPRs and per-wave conditions become scalar branches).
+__device__ __forceinline__ int wave_id()
+{
+    return __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+}
+
 // Workgroup index remapped so that each of the 8 XCDs (which receive
 // workgroups round-robin) works on one contiguous range of elements; vertices
 // shared by neighbouring elements are then gathered through the same L2.

@@ -18,30 +18,16 @@ namespace {
 
 constexpr int kBlock = 256;
 
-inline unsigned grid_for(int64_t E) { return unsigned((E + kBlock - 1) / kBlock); }
-
-template <typename K>
-int persistent_grid(K kernel, int64_t n_tiles);
-
-template <int F, int D, typename CT, int R>
-hipError_t launch_fwd_fma(const FwdParams &p, hipStream_t s)
-{
-    const int64_t n_tiles = (p.m.n_elements + kBlock - 1) / kBlock;
-    auto k = fwd_fma_kernel<F, D, CT, R>;
-    hipLaunchKernelGGL(k, dim3(persistent_grid(k, n_tiles)), dim3(kBlock), 0, s, p, n_tiles);
-    return hipGetLastError();
-}
-
 // Persistent grid: as many workgroups as fit on the device at once (queried
-// once per kernel), at most one per tile.
-template <typename K>
-int persistent_grid(K kernel, int64_t n_tiles)
+// once per kernel instantiation), at most one per tile.
+template <auto KERNEL>
+int persistent_grid(int64_t n_tiles)
 {
-    static const int64_t resident = [&]() -> int64_t {
+    static const int64_t resident = []() -> int64_t {
         int dev = 0, blocks = 0, n_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, kBlock, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, KERNEL, kBlock, 0) != hipSuccess ||
             blocks < 1 || n_cu < 1)
             return 256;
         return int64_t(blocks) * n_cu;
@@ -49,21 +35,34 @@ int persistent_grid(K kernel, int64_t n_tiles)
     return int(resident < n_tiles ? resident : n_tiles);
 }
 
+// A persistent kernel over tiles of TILE elements (a workgroup's 256, or a
+// wave's 64).
+template <auto KERNEL, int TILE = kBlock, typename P>
+hipError_t launch_persistent(const P &p, hipStream_t s)
+{
+    const int64_t n_tiles = (p.m.n_elements + TILE - 1) / TILE;
+    const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(KERNEL, dim3(persistent_grid<KERNEL>(n_groups)), dim3(kBlock), 0, s, p,
+                       n_tiles);
+    return hipGetLastError();
+}
+
+template <int F, int D, typename CT, int R>
+hipError_t launch_fwd_fma(const FwdParams &p, hipStream_t s)
+{
+    return launch_persistent<fwd_fma_kernel<F, D, CT, R>, 64>(p, s);
+}
+
 template <int F, int D, typename CT, int PREC, bool DIRECT>
 hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
 {
-    const int64_t n_tiles = (p.m.n_elements + kBlock - 1) / kBlock;
-    auto k = fwd_mfma_kernel<F, D, CT, PREC, DIRECT>;
-    hipLaunchKernelGGL(k, dim3(persistent_grid(k, n_tiles)), dim3(kBlock), 0, s, p, n_tiles);
-    return hipGetLastError();
+    return launch_persistent<fwd_mfma_kernel<F, D, CT, PREC, DIRECT>>(p, s);
 }
 
 template <int F, int D, typename CT, int R>
 hipError_t launch_adj_fma(const AdjParams &p, hipStream_t s)
 {
-    hipLaunchKernelGGL((adj_fma_kernel<F, D, CT, R>), dim3(grid_for(p.m.n_elements)),
-                       dim3(kBlock), 0, s, p);
-    return hipGetLastError();
+    return launch_persistent<adj_fma_kernel<F, D, CT, R>>(p, s);
 }
 
 // Staging rows R that fit: R divides n, R*n floats is a whole number of

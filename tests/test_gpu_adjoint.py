@@ -101,15 +101,18 @@ def test_adjoint_staging_modes(case, rows):
                                               vec_to_device(mu), vec_to_device(lam),
                                               store_rows=r, **_nan_coeff_buffers(mesh, form))
         outs.append((dc.cpu().numpy().T.astype(np.float64),
-                     None if dmu is None else dmu.cpu().numpy()))
+                     None if dmu is None else dmu.cpu().numpy(),
+                     None if dlam is None else dlam.cpu().numpy()))
     gv, gm, gl, _ = oracle.gradient(form, mesh.coords, mesh.conn, dA, mu, lam)
     go = oracle.vertex_gradient(gv, mesh.conn, mesh.n_vertices)
     scale = vertex_scale(gv, mesh.conn, mesh.n_vertices)
     used = scale > 0
-    for g, dmu in outs:
+    for g, dmu, dlam in outs:
         assert (np.abs(g - go).max(axis=1)[used] / scale[used]).max() <= TOL_VERTEX
-    if outs[0][1] is not None:   # per-element outputs need no atomics: identical bits
-        assert np.array_equal(outs[0][1].view(np.uint32), outs[1][1].view(np.uint32))
+        # per-element outputs: each mode against the oracle (the modes are
+        # separate kernel instantiations, whose multiply-add fusion may differ)
+        if dmu is not None:
+            assert _coeff_errors(mesh.coords, mesh.conn, dA, dmu, dlam, gm, gl).max() <= TOL_COEFF
 
 
 @pytest.mark.parametrize("flat", [False, True])
