@@ -97,7 +97,7 @@ typedef struct fei_mesh {
     int32_t dim;            /* 2 or 3 */
     int32_t coord_dtype;    /* FEI_F32 or FEI_F64 */
     int64_t n_vertices;     /* >= 1 unless n_elements == 0 */
-    int64_t n_elements;     /* >= 0 */
+    int64_t n_elements;     /* 0 <= n_elements <= 2^32 - 256 */
     const void *x;          /* device [n_vertices] coordinates (SoA) */
     const void *y;
     const void *z;          /* NULL when dim == 2 */

@@ -85,6 +85,9 @@ int check_mesh(const fei_mesh *m, MeshView &mv)
     if (m->coord_dtype != FEI_F32 && m->coord_dtype != FEI_F64)
         return fail(FEI_EINVAL, "unknown coord_dtype %d", m->coord_dtype);
     if (m->n_elements < 0) return fail(FEI_EINVAL, "n_elements < 0");
+    if (m->n_elements > kMaxElements)
+        return fail(FEI_EINVAL, "n_elements exceeds %lld (one launch covers at most 2^32 threads)",
+                    (long long)kMaxElements);
     if (m->n_elements > 0) {
         if (m->n_vertices < 1) return fail(FEI_EINVAL, "n_vertices < 1");
         if (m->n_vertices > int64_t(INT32_MAX) + 1)

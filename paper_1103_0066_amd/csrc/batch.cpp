@@ -218,11 +218,17 @@ int fei_batch_create(const fei_batch_item *items, int n_items, const fei_options
     const float tau2 = tau2_of(o.tau);
 
     std::vector<std::pair<double, BatchItemDev>> fwd, adj;
+    int64_t total = 0;
     for (int k = 0; k < n_items; ++k) {
         const fei_batch_item &it = items[k];
         MeshView mv;
         if ((rc = check_item(it, k, mv))) return rc;
         if (it.mesh.n_elements == 0) continue;
+        // each item rounds up to whole 256-element tiles; one launch covers them all
+        total += (it.mesh.n_elements + 255) / 256 * 256;
+        if (total > kMaxElements)
+            return fail(FEI_EINVAL, "the batch exceeds %lld elements in 256-element tiles",
+                        (long long)kMaxElements);
         BatchItemDev d;
         std::memset(&d, 0, sizeof d);
         d.form = it.form;

@@ -137,9 +137,9 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // One workgroup tile (256 elements, 4 waves) of the FP32 forward, in stages
-// (load -> gather -> compute -> store) so a persistent kernel can overlap
-// them across tiles.  LDS comes from the caller (LDS_BYTES, 16-byte aligned),
-// so one persistent kernel can also host the tiles of several forms.
+// (load -> gather -> compute -> store; each wave owns 64 consecutive
+// elements).  LDS comes from the caller (LDS_BYTES, 16-byte aligned), so one
+// persistent kernel can also host the tiles of several forms.
 template <int FORM, int DIM, typename CT, int R>
 struct FwdFmaTile {
     using T = Traits<FORM, DIM>;
@@ -147,10 +147,11 @@ struct FwdFmaTile {
     using U = Unique<FORM, DIM>;
     // R == N stages whole matrices, EC elements of the wave at a time, so each
     // chunk leaves as one contiguous run of EC matrices; R < N stages R rows of
-    // all 64 elements.  The 12 x 12 matrices go 32 at a time (76 KB of LDS per
-    // workgroup instead of 152 KB; measured faster than 64 or 16 at a time).
+    // all 64 elements.  The 12 x 12 and 10 x 10 matrices go 32 at a time (76
+    // and 53 KB of LDS per workgroup instead of 152 and 106 KB: two or three
+    // resident workgroups per CU; measured faster than 64 or 16 at a time).
     static constexpr bool WHOLE = (R == T::N);
-    static constexpr int EC = WHOLE ? (T::N == 12 ? 32 : 64) : 64;
+    static constexpr int EC = WHOLE ? (T::N >= 10 ? 32 : 64) : 64;
     static constexpr int NCH = WHOLE ? 64 / EC : S::NCHUNK;
     static constexpr int LDS_BYTES = (R > 0) ? 4 * EC * S::STR * 4 : 0;
 
@@ -308,95 +309,19 @@ struct PersistentTiles {
     }
 };
 
-// Wave tiles (64 elements) of a persistent grid: one contiguous range per
-// XCD that has workgroups (workgroups are dispatched round-robin over the 8
-// XCDs); the waves of an XCD take every (4 x workgroups)-th tile of its range.
-struct WaveTiles {
-    int64_t next_t, end, stride;
-    __device__ WaveTiles(int64_t n_tiles)
-    {
-        const int64_t G = gridDim.x, b = blockIdx.x;
-        const int64_t X = G < 8 ? G : 8;
-        const int64_t x = b % 8, i = b / 8;
-        const int64_t cnt = G / 8 + (x < G % 8 ? 1 : 0);
-        end = (x + 1) * n_tiles / X;
-        next_t = x * n_tiles / X + i * 4 + wave_id();
-        stride = 4 * cnt;
-    }
-    // next tile of this wave; >= end once the range is exhausted
-    __device__ int64_t pop()
-    {
-        const int64_t t = next_t;
-        next_t += stride;
-        return t;
-    }
-    __device__ void done() {}
-};
-
-#ifdef FEI_DYN
-__device__ unsigned long long g_dyn[2];
-struct DynTiles {
-    int64_t end;
-    __device__ DynTiles(int64_t n_tiles) : end(n_tiles) {}
-    __device__ int64_t pop()
-    {
-        unsigned long long v = 0;
-        if ((threadIdx.x & 63) == 0) v = atomicAdd(&g_dyn[0], 1ull);
-        return int64_t(__builtin_amdgcn_readfirstlane(unsigned(v)));
-    }
-    __device__ void done()
-    {
-        if ((threadIdx.x & 63) == 0) {
-            const unsigned long long d = atomicAdd(&g_dyn[1], 1ull);
-            if (d + 1 == 4ull * gridDim.x) {
-                atomicExch(&g_dyn[0], 0ull);
-                atomicExch(&g_dyn[1], 0ull);
-            }
-        }
-    }
-};
-#endif
-
-// Persistent, software-pipelined FP32 forward over wave tiles.  Vector-memory
-// loads and stores complete in issue order for s_waitcnt, so waiting on a
-// load issued after a tile's stores would wait for those stores.  Each
-// iteration therefore issues the next tile's coordinate gather and the
-// connectivity of the tile after it BEFORE storing the current tile, and only
-// then waits for them: the stores drain while the next tile is computed.
-// Only the connectivity is carried across iterations, and the old copy is
-// dead once gathered, so the two share registers.
+// FP32 forward: one workgroup per 256-element tile, tiles remapped so that
+// each XCD integrates one contiguous range of elements (its L2 then holds the
+// shared vertices, and each XCD's stores sweep one region of A).  Several
+// workgroups are resident per CU (the whole-matrix staging keeps LDS at or
+// below 76 KB), so the hardware overlaps one workgroup's gathers and
+// contraction with another's stores; measured faster on MI355X than a
+// persistent, software-pipelined loop over tiles with one wave per SIMD.
 template <int FORM, int DIM, typename CT, int R>
-__global__ __launch_bounds__(256) void fwd_fma_kernel(FwdParams p, int64_t n_tiles)
+__global__ __launch_bounds__(256) void fwd_fma_kernel(FwdParams p)
 {
     using Tile = FwdFmaTile<FORM, DIM, CT, R>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES > 0 ? Tile::LDS_BYTES : 16];
-#ifdef FEI_DYN
-    DynTiles ws(n_tiles);
-#else
-    WaveTiles ws(n_tiles);
-#endif
-    int64_t t = ws.pop();
-    if (t < ws.end) {
-        float Au[Unique<FORM, DIM>::NU];
-        {
-            const typename Tile::Xv g = Tile::gather_xv(p, t * 64, Tile::load(p, t * 64));
-            Tile::compute(p, t * 64, g, Au);
-        }
-        int64_t tn = ws.pop();
-        typename Tile::In conn = Tile::load(p, tn * 64);
-        for (;;) {
-            const typename Tile::Xv g = Tile::gather_xv(p, tn * 64, conn);
-            const bool more = tn < ws.end;
-            const int64_t tnn = more ? ws.pop() : tn;
-            conn = Tile::load(p, tnn * 64);
-            Tile::store(p, t * 64, Au, smem);
-            if (!more) break;
-            Tile::compute(p, tn * 64, g, Au);
-            t = tn;
-            tn = tnn;
-        }
-    }
-    ws.done();
+    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
 }
 
 }  // namespace fei

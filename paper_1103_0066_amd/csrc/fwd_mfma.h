@@ -278,15 +278,22 @@ struct MfmaTile {
     }
 };
 
-template <int FORM, int DIM, typename CT, int PREC, bool DIRECT>
+// PERSISTENT: a grid of resident workgroups loops over the tiles (split per
+// XCD), loading the K fragments once; otherwise one workgroup per tile
+// (tiles remapped per XCD).
+template <int FORM, int DIM, typename CT, int PREC, bool DIRECT, bool PERSISTENT>
 __global__ __launch_bounds__(256) void fwd_mfma_kernel(FwdParams p, int64_t n_tiles)
 {
     using Tile = MfmaTile<FORM, DIM, CT, PREC, DIRECT>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
     typename Tile::Frags a;
     Tile::load_frags(a, smem);
-    const PersistentTiles pt(n_tiles);
-    for (int64_t t = pt.begin; t < pt.end; t += pt.stride) Tile::run(p, t, smem, a);
+    if constexpr (PERSISTENT) {
+        const PersistentTiles pt(n_tiles);
+        for (int64_t t = pt.begin; t < pt.end; t += pt.stride) Tile::run(p, t, smem, a);
+    } else {
+        Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem, a);
+    }
 }
 
 }  // namespace fei

@@ -12,6 +12,10 @@
 namespace fei {
 namespace host {
 
+// Largest mesh one call accepts: a launch covers at most 2^32 threads, one per
+// element (grids of 256-thread workgroups).
+constexpr int64_t kMaxElements = (int64_t(1) << 32) - 256;
+
 int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int hip_fail(hipError_t e, const char *what);
 bool aligned(const void *p, size_t a);

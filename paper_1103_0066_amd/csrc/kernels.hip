@@ -35,14 +35,12 @@ int persistent_grid(int64_t n_tiles)
     return int(resident < n_tiles ? resident : n_tiles);
 }
 
-// A persistent kernel over tiles of TILE elements (a workgroup's 256, or a
-// wave's 64).
-template <auto KERNEL, int TILE = kBlock, typename P>
+// A persistent kernel over the 256-element workgroup tiles.
+template <auto KERNEL, typename P>
 hipError_t launch_persistent(const P &p, hipStream_t s)
 {
-    const int64_t n_tiles = (p.m.n_elements + TILE - 1) / TILE;
-    const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(KERNEL, dim3(persistent_grid<KERNEL>(n_groups)), dim3(kBlock), 0, s, p,
+    const int64_t n_tiles = (p.m.n_elements + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(KERNEL, dim3(persistent_grid<KERNEL>(n_tiles)), dim3(kBlock), 0, s, p,
                        n_tiles);
     return hipGetLastError();
 }
@@ -50,13 +48,26 @@ hipError_t launch_persistent(const P &p, hipStream_t s)
 template <int F, int D, typename CT, int R>
 hipError_t launch_fwd_fma(const FwdParams &p, hipStream_t s)
 {
-    return launch_persistent<fwd_fma_kernel<F, D, CT, R>, 64>(p, s);
+    const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((fwd_fma_kernel<F, D, CT, R>), dim3(unsigned(n_groups)), dim3(kBlock), 0, s,
+                       p);
+    return hipGetLastError();
 }
 
+// MFMA forward: one workgroup per tile for the two-term splits; the
+// three-term split keeps its larger K fragment set in registers across tiles
+// of a persistent grid (each measured the faster for its form on MI355X).
 template <int F, int D, typename CT, int PREC, bool DIRECT>
 hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
 {
-    return launch_persistent<fwd_mfma_kernel<F, D, CT, PREC, DIRECT>>(p, s);
+    if constexpr (PREC == P_BF16X3) {
+        return launch_persistent<fwd_mfma_kernel<F, D, CT, PREC, DIRECT, true>>(p, s);
+    } else {
+        const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL((fwd_mfma_kernel<F, D, CT, PREC, DIRECT, false>), dim3(unsigned(n_groups)),
+                           dim3(kBlock), 0, s, p, n_groups);
+        return hipGetLastError();
+    }
 }
 
 template <int F, int D, typename CT, int R>

@@ -155,7 +155,7 @@ def test_options_default():
     assert o.precision == 0 and math.isclose(o.tau, 100.0) and not o.counters
 
 
-@pytest.mark.parametrize("case", ["null_mesh", "bad_dim", "bad_dtype", "neg_E", "bad_form",
+@pytest.mark.parametrize("case", ["null_mesh", "bad_dim", "bad_dtype", "neg_E", "huge_E", "bad_form",
                                   "mu_for_laplace", "missing_mu", "bad_precision", "nan_tau",
                                   "reserved", "null_A", "misaligned_A", "null_conn",
                                   "misaligned_conn", "null_z", "zero_nv"])
@@ -170,6 +170,8 @@ def test_integrate_rejects(case):
         m.coord_dtype = 7
     elif case == "neg_E":
         m.n_elements = -1
+    elif case == "huge_E":          # one launch covers at most 2^32 threads
+        m.n_elements = 2 ** 32
     elif case == "bad_form":
         kw["form"] = 9
     elif case == "mu_for_laplace":
