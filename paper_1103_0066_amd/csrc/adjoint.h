@@ -490,11 +490,13 @@ struct AdjTile {
         scatter_vertices<DIM>(p, in.v, o.Jbar, valid, L.key, L.val, lane);
     }
 
-    // The whole tile in order (batch kernels).
+    // One tile on its own (batch kernels): chunk c + 1 is loaded while chunk c
+    // is folded, and chunk 0 travels with the connectivity and coordinates.
     __device__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem)
     {
         const Lds L = lds(smem);
         const In in = load(p, blk);
+        Chunk ch = load_chunk(p, blk, 0);
         const Xv g = gather_xv(p, blk, in);
         const unsigned long long fm = __ballot(flagged(p, blk, g));
         AccT U[T::G];
@@ -502,7 +504,12 @@ struct AdjTile {
         for (int k = 0; k < T::G; ++k) U[k] = AccT(0);
         if constexpr (R > 0) {
 #pragma unroll
-            for (int c = 0; c < S::NCHUNK; ++c) fold_chunk(L, c, load_chunk(p, blk, c), fm, U);
+            for (int c = 0; c < S::NCHUNK; ++c) {
+                Chunk nx;
+                if (c + 1 < S::NCHUNK) nx = load_chunk(p, blk, c + 1);
+                fold_chunk(L, c, ch, fm, U);
+                if (c + 1 < S::NCHUNK) ch = nx;
+            }
         } else {
             fold_direct(p, blk, U);
         }

@@ -14,10 +14,21 @@
 
 namespace fei {
 
-// Staging rows per form for the two batch variants: 0 keeps every form's
-// LDS at or below 64 KB (several workgroups per CU), 1 keeps it near 28 KB.
+// Staging rows per form for the two batch variants.  Forward: 0 stages whole
+// matrices (the single-mesh default, at most 76 KB of LDS per workgroup), 1
+// two rows at a time (near 28 KB).  Adjoint: 0 keeps LDS at or below 92 KB,
+// 1 near 28 KB.
 template <int F, int D, int VAR>
 constexpr int batch_rows()
+{
+    constexpr int N = Traits<F, D>::N;
+    if constexpr (N == 3) return 0;
+    else if constexpr (VAR == 0) return N;
+    else return 2;
+}
+
+template <int F, int D, int VAR>
+constexpr int batch_adj_rows()
 {
     constexpr int N = Traits<F, D>::N;
     if constexpr (N == 3) return 0;
@@ -40,7 +51,7 @@ struct BatchFwdTile {
 
 template <int F, int D, int VAR>
 struct BatchAdjTile {
-    using Tile = AdjTile<F, D, float, batch_rows<F, D, VAR>()>;
+    using Tile = AdjTile<F, D, float, batch_adj_rows<F, D, VAR>()>;
     static constexpr int LDS_BYTES = Tile::LDS_BYTES;
 };
 

@@ -100,7 +100,7 @@ template <int F, int D>
 constexpr int default_adj_rows()
 {
     constexpr int N = Traits<F, D>::N;
-    if constexpr (N == 12) return 3;
+    if constexpr (N == 12) return 4;
     else if constexpr (N == 4) return 4;
     else if constexpr (N == 10 || N == 6) return 2;
     else return 0;
