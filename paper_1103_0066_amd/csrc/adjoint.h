@@ -492,7 +492,7 @@ struct AdjTile {
 
     // One tile on its own (batch kernels): chunk c + 1 is loaded while chunk c
     // is folded, and chunk 0 travels with the connectivity and coordinates.
-    __device__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem)
+    __device__ __forceinline__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem)
     {
         const Lds L = lds(smem);
         const In in = load(p, blk);

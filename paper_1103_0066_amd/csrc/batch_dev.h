@@ -42,7 +42,7 @@ struct BatchFwdTile {
     using Fma = FwdFmaTile<F, D, float, batch_rows<F, D, VAR>()>;
     using Mfma = MfmaTile<F, D, float, (PREC == P_FP32 ? P_FP16X2 : PREC), VAR == 1>;
     static constexpr int LDS_BYTES = (PREC == P_FP32) ? Fma::LDS_BYTES : Mfma::LDS_BYTES;
-    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    __device__ __forceinline__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
     {
         if constexpr (PREC == P_FP32) Fma::run(p, blk, smem);
         else Mfma::run(p, blk, smem);

@@ -280,7 +280,7 @@ struct FwdFmaTile {
     }
 
     // The whole tile in order (batch kernels).
-    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    __device__ __forceinline__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
     {
         const int64_t e0 = blk * 256 + wave_id() * 64;
         const Xv g = gather_xv(p, e0, load(p, e0));

@@ -150,7 +150,7 @@ struct MfmaTile {
     }
 
     // LDS: [K fragments] | per-wave split-Gf rows / output staging | FP16 exponents
-    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem, const Frags &a)
+    __device__ __forceinline__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem, const Frags &a)
     {
         const int tid = threadIdx.x;
         const int lane = tid & 63, wave = tid >> 6;
@@ -270,7 +270,7 @@ struct MfmaTile {
     }
 
     // One tile without preloaded fragments (batch kernels).
-    __device__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    __device__ __forceinline__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
     {
         Frags a;
         load_frags(a, smem);
