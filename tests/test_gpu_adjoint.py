@@ -115,6 +115,30 @@ def test_adjoint_staging_modes(case, rows):
             assert _coeff_errors(mesh.coords, mesh.conn, dA, dmu, dlam, gm, gl).max() <= TOL_COEFF
 
 
+@pytest.mark.parametrize("rows", [0, -1, 2])
+def test_adjoint_every_tile_count_is_covered(rows):
+    """1 to 11 workgroup tiles (the persistent adjoint splits tiles over the XCDs
+    that have workgroups): every element and vertex contribution counted once."""
+    m = meshgen.flatten_elements(meshgen.cube_mesh(8, 8, 8, 0.15, 61), 20, 62)
+    mu, lam = meshgen.lame(m.n_elements, 63)
+    for E in (1, 63, 255, 256, 257, 3 * 256 + 5, 7 * 256, 8 * 256 + 1, 9 * 256 + 100, 2600):
+        sub = meshgen.Mesh(m.coords, np.ascontiguousarray(m.conn[:E]))
+        dA = meshgen.upstream(E, 12, 64 + E)
+        coords, conn = mesh_to_device(sub)
+        dc, dmu, dlam = fei.integrate_adjoint(coords, conn, "elastic_p1", vec_to_device(dA),
+                                              vec_to_device(mu[:E]), vec_to_device(lam[:E]),
+                                              store_rows=rows, **_nan_coeff_buffers(sub, "elastic_p1"))
+        g = dc.cpu().numpy().T.astype(np.float64)
+        gv, gm, gl, _ = oracle.gradient("elastic_p1", m.coords, sub.conn, dA, mu[:E], lam[:E])
+        go = oracle.vertex_gradient(gv, sub.conn, m.n_vertices)
+        scale = vertex_scale(gv, sub.conn, m.n_vertices)
+        used = scale > 0
+        assert np.all(g[~used] == 0), E                      # untouched vertices stay zero
+        assert (np.abs(g - go).max(axis=1)[used] / scale[used]).max() <= TOL_VERTEX, E
+        assert _coeff_errors(m.coords, sub.conn, dA, dmu.cpu().numpy(), dlam.cpu().numpy(),
+                             gm, gl).max() <= TOL_COEFF, E
+
+
 @pytest.mark.parametrize("flat", [False, True])
 def test_adjoint_fd_submesh(flat):
     """The 48-tet sub-mesh: GPU vs the oracle gradient and FP64 central differences."""
