@@ -118,8 +118,11 @@ typedef struct fei_options {
                                0 = the tuned default; -1 = every lane stores
                                its own rows; R > 0 = the wave stages R rows of
                                all its elements' matrices in LDS and stores
-                               them with contiguous 16-byte pieces (the adjoint
-                               reads dA the same way).  R must divide n with
+                               them with contiguous 16-byte pieces; R = n
+                               stages whole matrices, which leave as one
+                               contiguous run per chunk of elements (the
+                               forward's default; the adjoint reads dA in R-row
+                               chunks the same way).  R must divide n with
                                R*n a multiple of 4; FEI_EUNSUPPORTED otherwise. */
     int32_t reserved[4];    /* must be zero */
 } fei_options;

@@ -14,8 +14,9 @@
 // Workgroup = 4 waves = 256 elements.  Phase 1 is the FP32 path's geometry,
 // one lane per element, writing the split Gf row of its element into LDS.
 // Phase 2: each wave multiplies its 64 elements as 4 groups of 16 MFMA
-// columns.  The K fragments (the MFMA A operand) are precomputed at compile
-// time in lane order and staged in LDS once per workgroup.  The MFMA output
+// columns.  The K fragments (the MFMA A operand) are precomputed at build
+// time in lane order and held in registers (staged in LDS once per workgroup
+// if they would not fit).  The MFMA output
 // puts 4 consecutive entries of one element in each lane, which are stored
 // as one 16-byte vector (64 contiguous bytes per element per M tile).
 #pragma once
@@ -107,14 +108,15 @@ struct MfmaLds {
     static constexpr int BBYTES = 64 * S::BROW * 2;           // split-Gf rows of a wave
     static constexpr int OBYTES = STAGED ? 16 * OSTR * 4 : 0;  // 16 staged matrices
     static constexpr int WBYTES = ((BBYTES > OBYTES ? BBYTES : OBYTES) + 15) / 16 * 16;
-    // K fragments live in registers when they take at most 128 VGPRs, else in LDS
-    static constexpr bool AREG = S::MT * S::KS <= 32;
+    // K fragments live in registers when they take at most 192 VGPRs (all the
+    // forms here; measured faster than LDS-staged fragments), else in LDS
+    static constexpr bool AREG = S::MT * S::KS <= 48;
 };
 
 // One workgroup tile (256 elements, 4 waves) of the MFMA forward.  Waves only
 // touch their own LDS rows, so the phases are ordered per wave, not per
-// workgroup; the K fragments are loaded once (load_frags) and reused for
-// every tile a persistent workgroup processes.
+// workgroup; the K fragments are loaded once per workgroup (load_frags) and
+// reused for every tile it processes.
 template <int FORM, int DIM, typename CT, int PREC, bool DIRECT>
 struct MfmaTile {
     using T = Traits<FORM, DIM>;

@@ -54,13 +54,14 @@ hipError_t launch_fwd_fma(const FwdParams &p, hipStream_t s)
     return hipGetLastError();
 }
 
-// MFMA forward: one workgroup per tile for the two-term splits; the
-// three-term split keeps its larger K fragment set in registers across tiles
-// of a persistent grid (each measured the faster for its form on MI355X).
+// MFMA forward: one workgroup per tile, except for fragment sets above 32
+// per lane (3D elasticity in BF16x3: 45), which a persistent grid loads once
+// per workgroup instead of once per tile (each measured the faster for its
+// form on MI355X).
 template <int F, int D, typename CT, int PREC, bool DIRECT>
 hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
 {
-    if constexpr (PREC == P_BF16X3) {
+    if constexpr (MfmaShape<F, D, PREC>::MT * MfmaShape<F, D, PREC>::KS > 32) {
         return launch_persistent<fwd_mfma_kernel<F, D, CT, PREC, DIRECT, true>>(p, s);
     } else {
         const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
