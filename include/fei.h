@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define FEI_ABI_VERSION 1
+#define FEI_ABI_VERSION 2
 
 enum fei_status {
     FEI_OK = 0,
@@ -194,10 +194,11 @@ int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream);
  *      own form only).
  * fei_batch_tune times candidate configurations on the caller's data and
  * rebuilds the graph with the fastest.
- * The plan owns only its descriptor table, work counter, streams and graphs
- * (allocated by fei_batch_create, released by fei_batch_destroy); every
- * pointer in the items is caller memory that must outlive the plan.  Only
- * FP32 coordinates are accepted in batches.                                */
+ * The plan owns its descriptor tables, work counter, streams and graphs, and
+ * for the adjoint's vertex gather its incidence and J-bar buffers (allocated
+ * by fei_batch_create, fei_batch_tune or fei_batch_set_config, released by
+ * fei_batch_destroy); every pointer in the items is caller memory that must
+ * outlive the plan.  Only FP32 coordinates are accepted in batches.        */
 typedef struct fei_batch_item {
     fei_mesh mesh;
     int32_t form;
@@ -215,7 +216,19 @@ typedef struct fei_batch_config {
     int32_t workgroups;     /* mode 0: persistent workgroups launched */
     int32_t tiles_per_pop;  /* mode 0: tiles taken from the counter per atomic */
     float ms;               /* measured time of this configuration (0: not tuned) */
-    int32_t reserved[3];
+    int32_t gather;         /* adjoint only.  0: vertex gradients by a wave-level
+                               merge, then global FP32 atomics (they execute at
+                               the memory side); 1: J-bar per element into a
+                               plan buffer, then each vertex sums its
+                               elements' terms in an order fixed by the mesh --
+                               no atomics (unless two items share gradient
+                               arrays), and the result does not depend on the
+                               launch.  Setting 1 first builds the plan's
+                               vertex-to-element incidence from the items'
+                               connectivity (device-synchronizing; the plan
+                               then holds 4 (N_v + 1) + 4 (d + 1) E + 4 d^2 E
+                               bytes per item). */
+    int32_t reserved[2];    /* must be zero */
 } fei_batch_config;
 
 typedef struct fei_batch fei_batch;
@@ -229,14 +242,16 @@ int fei_batch_create(const fei_batch_item *items, int n_items, const fei_options
 int fei_batch_run(fei_batch *b, void *stream);
 int fei_batch_run_adjoint(fei_batch *b, void *stream);
 /* Times the candidate configurations of the forward (adjoint = 0) or adjoint
- * (adjoint = 1) graph on `stream` -- running them, so outputs are written,
- * and for the adjoint dx/dy/dz receive one accumulation per trial -- then
- * rebuilds that graph with the fastest.  *chosen (if not NULL) receives it. */
+ * (adjoint = 1, both gather settings: builds the vertex incidence first) graph
+ * on `stream` -- running them, so outputs are written, and for the adjoint
+ * dx/dy/dz receive one accumulation per trial -- then rebuilds that graph with
+ * the fastest.  *chosen (if not NULL) receives it.                           */
 int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *chosen);
 int fei_batch_get_config(const fei_batch *b, int adjoint, fei_batch_config *out);
 /* Rebuilds the forward/adjoint graph with a given configuration (for example
  * one returned by an earlier fei_batch_tune).  mode 0 needs workgroups >= 1
- * and tiles_per_pop >= 1; variant is 0 or 1.                                */
+ * and tiles_per_pop >= 1; variant and gather are 0 or 1 (gather = 1 only for
+ * the adjoint); reserved must be zero.                                      */
 int fei_batch_set_config(fei_batch *b, int adjoint, const fei_batch_config *cfg);
 int fei_batch_destroy(fei_batch *b);
 

@@ -20,6 +20,8 @@ LAYOUT_FOLDED = 1
 F32 = 0
 F64 = 1
 
+ABI_VERSION = 2          # FEI_ABI_VERSION of the structs below
+
 EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_default",
            "fei_local_size", "fei_reference_tensor", "fei_reference_scale", "fei_integrate",
            "fei_integrate_adjoint", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
@@ -50,12 +52,13 @@ class FeiBatchItem(ctypes.Structure):
 class FeiBatchConfig(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("workgroups", ctypes.c_int32), ("tiles_per_pop", ctypes.c_int32),
-                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+                ("ms", ctypes.c_float), ("gather", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 def config_dict(c: "FeiBatchConfig") -> dict:
     return {"mode": c.mode, "variant": c.variant, "workgroups": c.workgroups,
-            "tiles_per_pop": c.tiles_per_pop, "ms": c.ms}
+            "tiles_per_pop": c.tiles_per_pop, "ms": c.ms, "gather": c.gather}
 
 
 class FeiError(RuntimeError):
@@ -80,6 +83,9 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, f32p = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.fei_abi_version.restype = ctypes.c_int
+    if lib.fei_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} implements ABI {lib.fei_abi_version()}, this binding "
+                          f"ABI {ABI_VERSION}: rebuild the library")
     lib.fei_status_str.restype = ctypes.c_char_p
     lib.fei_status_str.argtypes = [ctypes.c_int]
     lib.fei_last_error.restype = ctypes.c_char_p

@@ -65,7 +65,8 @@ class Batch:
     def tune(self, adjoint: bool = False, stream: Optional[torch.cuda.Stream] = None) -> dict:
         """Time the candidate graph shapes on this batch and keep the fastest.
         Runs the batch (outputs are written; for the adjoint the gradients are
-        accumulated once per trial)."""
+        accumulated once per trial, and both the atomic scatter and the vertex
+        gather -- ``gather`` in the returned config -- are tried)."""
         c = _lib.FeiBatchConfig()
         _lib.check(_lib.load().fei_batch_tune(self._h, int(adjoint), self._stream(stream),
                                               ctypes.byref(c)))
@@ -82,6 +83,7 @@ class Batch:
         c.workgroups = int(cfg.get("workgroups", 0))
         c.tiles_per_pop = int(cfg.get("tiles_per_pop", 1))
         c.ms = float(cfg.get("ms", 0.0))
+        c.gather = int(cfg.get("gather", 0))
         _lib.check(_lib.load().fei_batch_set_config(self._h, int(adjoint), ctypes.byref(c)))
 
     def close(self):

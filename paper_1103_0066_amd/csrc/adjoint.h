@@ -487,7 +487,33 @@ struct AdjTile {
             if (valid && p.dmu) p.dmu[e] = o.mubar;
             if (valid && p.dlam) p.dlam[e] = o.lambar;
         }
-        scatter_vertices<DIM>(p, in.v, o.Jbar, valid, L.key, L.val, lane);
+        if (p.jbar) {
+            // J-bar per element, gathered per vertex by a later kernel.  A full
+            // wave's 64 blocks of DIM^2 floats are one contiguous run: staged
+            // in LDS and stored as 16-byte pieces; otherwise lane by lane.
+            constexpr int JN = DIM * DIM;
+            const int64_t e0 = e - lane;
+            if (SW >= 64 * JN && e0 + 64 <= p.m.n_elements) {
+#pragma unroll
+                for (int al = 0; al < DIM; ++al)
+#pragma unroll
+                    for (int m = 0; m < DIM; ++m) L.st[lane * JN + al * DIM + m] = o.Jbar[al][m];
+                wave_sync();
+                f32x4_t *dst = reinterpret_cast<f32x4_t *>(p.jbar + e0 * JN);
+                const f32x4_t *src = reinterpret_cast<const f32x4_t *>(L.st);
+#pragma unroll
+                for (int f = lane; f < 16 * JN; f += 64) dst[f] = src[f];
+                wave_sync();
+            } else if (valid) {
+                float *J = p.jbar + e * JN;
+#pragma unroll
+                for (int al = 0; al < DIM; ++al)
+#pragma unroll
+                    for (int m = 0; m < DIM; ++m) J[al * DIM + m] = o.Jbar[al][m];
+            }
+        } else {
+            scatter_vertices<DIM>(p, in.v, o.Jbar, valid, L.key, L.val, lane);
+        }
     }
 
     // One tile on its own (batch kernels): chunk c + 1 is loaded while chunk c

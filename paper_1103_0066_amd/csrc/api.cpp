@@ -287,6 +287,7 @@ int fei_integrate_adjoint(const fei_mesh *m, int form, const float *mu, const fl
     p.dlam = dlam;
     p.counters = o.counters;
     p.tau2 = tau2_of(o.tau);
+    p.jbar = nullptr;
     hipError_t e = launch(p, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
     return FEI_OK;

@@ -31,9 +31,22 @@ struct Side {
     int64_t tiles = 0;
     BatchItemDev *d_all = nullptr;
     BatchItemDev *d_grouped = nullptr;
+    // adjoint with the vertex gather: the same descriptors with J-bar buffers
+    std::vector<BatchItemDev> grouped_g;
+    BatchItemDev *d_all_g = nullptr;
+    BatchItemDev *d_grouped_g = nullptr;
     fei_batch_config cfg{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+};
+
+// Vertex-gather state of the adjoint side, built on first use.
+struct Gather {
+    bool ready = false;
+    std::vector<void *> bufs;           // device allocations owned by the plan
+    GatherItem *d_items = nullptr;
+    int n_items = 0;
+    int64_t n_total = 0;                // vertices over all items
 };
 
 double item_bytes(const fei_batch_item &it)
@@ -52,6 +65,7 @@ struct fei_batch {
     int n_cu = 0;
     int precision = 0;
     Side side[2];
+    Gather gather;
     int32_t *d_counter = nullptr;  // [0] forward, [1] adjoint
     hipStream_t cap = nullptr;
     hipStream_t branch[6] = {};
@@ -108,30 +122,133 @@ void layout(Side &sd, std::vector<std::pair<double, BatchItemDev>> items)
 }
 
 // Enqueues one run of a side with configuration c on stream s.
+// (with c.gather on the adjoint side: J-bar per element, then the vertex gather)
 hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t s)
 {
     Side &sd = b->side[adj];
     const int prec = adj ? int(P_FP32) : b->precision;
     if (sd.tiles == 0) return hipSuccess;
+    const bool gather = adj && c.gather;
+    if (gather && !b->gather.ready) return hipErrorInvalidValue;
+    const BatchItemDev *all = gather ? sd.d_all_g : sd.d_all;
+    const BatchItemDev *grouped = gather ? sd.d_grouped_g : sd.d_grouped;
+    hipError_t e = hipSuccess;
     if (c.mode == 0) {
-        BatchLaunch L{sd.d_all, int32_t(sd.all.size()), c.tiles_per_pop, sd.tiles, b->d_counter + adj};
-        hipError_t e = launch_batch_reset(L.counter, s);
-        if (e != hipSuccess) return e;
-        return launch_batch(adj != 0, prec, c.variant, L, c.workgroups, s);
+        BatchLaunch L{all, int32_t(sd.all.size()), c.tiles_per_pop, sd.tiles, b->d_counter + adj};
+        if ((e = launch_batch_reset(L.counter, s)) != hipSuccess) return e;
+        if ((e = launch_batch(adj != 0, prec, c.variant, L, c.workgroups, s)) != hipSuccess) return e;
+    } else {
+        if ((e = hipEventRecord(b->fork, s)) != hipSuccess) return e;
+        for (size_t g = 0; g < sd.groups.size(); ++g) {
+            const Group &G = sd.groups[g];
+            hipStream_t bs = b->branch[g];
+            if ((e = hipStreamWaitEvent(bs, b->fork, 0)) != hipSuccess) return e;
+            if (adj && G.n == 1) {
+                // a group of one mesh: the single-mesh adjoint (persistent,
+                // with cross-tile prefetch) on that item's parameters
+                const BatchItemDev &d = gather ? sd.grouped_g[G.off] : sd.grouped[G.off];
+                const AdjLauncher run = find_adjoint(Variant{d.form, d.dim, 0, P_FP32, 0});
+                if (!run) return hipErrorInvalidValue;
+                if ((e = run(d.ap, bs)) != hipSuccess) return e;
+            } else {
+                BatchLaunch L{grouped + G.off, G.n, 1, G.tiles, nullptr};
+                if ((e = launch_batch_group(adj != 0, G.form, G.dim, prec, c.variant, L, bs)) !=
+                    hipSuccess)
+                    return e;
+            }
+            if ((e = hipEventRecord(b->join[g], bs)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, b->join[g], 0)) != hipSuccess) return e;
+        }
     }
-    hipError_t e = hipEventRecord(b->fork, s);
-    if (e != hipSuccess) return e;
-    for (size_t g = 0; g < sd.groups.size(); ++g) {
-        const Group &G = sd.groups[g];
-        hipStream_t bs = b->branch[g];
-        if ((e = hipStreamWaitEvent(bs, b->fork, 0)) != hipSuccess) return e;
-        BatchLaunch L{sd.d_grouped + G.off, G.n, 1, G.tiles, nullptr};
-        if ((e = launch_batch_group(adj != 0, G.form, G.dim, prec, c.variant, L, bs)) != hipSuccess)
-            return e;
-        if ((e = hipEventRecord(b->join[g], bs)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(s, b->join[g], 0)) != hipSuccess) return e;
+    if (gather) e = launch_vertex_gather(b->gather.d_items, b->gather.n_items, b->gather.n_total, s);
+    return e;
+}
+
+// Builds the vertex gather of the adjoint side: per item the vertex-to-element
+// incidence of its mesh and a J-bar buffer, the descriptor copies that point
+// at those buffers, and the gather table.  Reads the items' connectivity after
+// synchronizing the device.
+int ensure_gather(fei_batch *b)
+{
+    Gather &G = b->gather;
+    if (G.ready) return FEI_OK;
+    Side &sd = b->side[1];
+    auto alloc = [&](size_t bytes, void **p) -> int {
+        hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 4);
+        if (e != hipSuccess) return fail(FEI_ENOMEM, "vertex gather buffers: %s", hipGetErrorString(e));
+        G.bufs.push_back(*p);
+        return FEI_OK;
+    };
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronize before the incidence build");
+    std::vector<GatherItem> items;
+    std::vector<std::pair<int32_t, float *>> jbar_of;   // item key -> J-bar buffer
+    std::vector<void *> scratch;
+    int rc = FEI_OK;
+    for (const BatchItemDev &d : sd.all) {
+        const int nv = d.dim + 1;
+        const int64_t E = d.ap.m.n_elements, Nv = d.ap.m.n_vertices;
+        if (E * nv > int64_t(INT32_MAX))
+            return fail(FEI_EUNSUPPORTED, "vertex gather needs (dim+1) * n_elements < 2^31");
+        int32_t *ptr = nullptr, *inc = nullptr, *cursor = nullptr;
+        float *jbar = nullptr;
+        if ((rc = alloc(size_t(Nv + 1) * 4, reinterpret_cast<void **>(&ptr))) ||
+            (rc = alloc(size_t(E) * nv * 4, reinterpret_cast<void **>(&inc))) ||
+            (rc = alloc(size_t(E) * d.dim * d.dim * 4, reinterpret_cast<void **>(&jbar))))
+            return rc;
+        if ((e = hipMalloc(reinterpret_cast<void **>(&cursor), size_t(Nv > 0 ? Nv : 1) * 4)) != hipSuccess)
+            return fail(FEI_ENOMEM, "incidence scratch: %s", hipGetErrorString(e));
+        scratch.push_back(cursor);
+        Incidence inc_g{d.ap.m.conn, E, Nv, nv, ptr, inc, cursor};
+        if ((e = launch_incidence_build(inc_g, b->cap)) != hipSuccess) break;
+        GatherItem gi{};
+        gi.ptr = ptr;
+        gi.inc = inc;
+        gi.jbar = jbar;
+        gi.dx = d.ap.dx;
+        gi.dy = d.ap.dy;
+        gi.dz = d.ap.dz;
+        gi.v_begin = G.n_total;
+        gi.n_vertices = Nv;
+        gi.dim = d.dim;
+        gi.atomic = 0;
+        items.push_back(gi);
+        jbar_of.push_back({d.key, jbar});
+        G.n_total += Nv;
     }
-    return hipSuccess;
+    if (e == hipSuccess) e = hipStreamSynchronize(b->cap);
+    for (void *p : scratch) hipFree(p);
+    if (e != hipSuccess) return hip_fail(e, "incidence build");
+    // items whose gradient arrays overlap another item's accumulate atomically
+    auto overlaps = [](const GatherItem &a, const GatherItem &c) {
+        const float *pa[3] = {a.dx, a.dy, a.dz}, *pc[3] = {c.dx, c.dy, c.dz};
+        for (int i = 0; i < a.dim; ++i)
+            for (int j = 0; j < c.dim; ++j)
+                if (pa[i] < pc[j] + c.n_vertices && pc[j] < pa[i] + a.n_vertices) return true;
+        return false;
+    };
+    for (size_t i = 0; i < items.size(); ++i)
+        for (size_t j = 0; j < items.size(); ++j)
+            if (i != j && overlaps(items[i], items[j])) items[i].atomic = 1;
+    auto with_jbar = [&](std::vector<BatchItemDev> v) {
+        for (BatchItemDev &d : v)
+            for (auto &kj : jbar_of)
+                if (kj.first == d.key) d.ap.jbar = kj.second;
+        return v;
+    };
+    sd.grouped_g = with_jbar(sd.grouped);
+    if ((rc = upload(with_jbar(sd.all), &sd.d_all_g)) || (rc = upload(sd.grouped_g, &sd.d_grouped_g)))
+        return rc;
+    G.n_items = int(items.size());
+    if (!items.empty()) {
+        if ((rc = alloc(items.size() * sizeof(GatherItem), reinterpret_cast<void **>(&G.d_items))))
+            return rc;
+        e = hipMemcpy(G.d_items, items.data(), items.size() * sizeof(GatherItem),
+                      hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "gather table upload");
+    }
+    G.ready = true;
+    return FEI_OK;
 }
 
 void drop_graph(Side &sd)
@@ -170,7 +287,10 @@ void release(fei_batch *b)
         drop_graph(sd);
         if (sd.d_all) hipFree(sd.d_all);
         if (sd.d_grouped) hipFree(sd.d_grouped);
+        if (sd.d_all_g) hipFree(sd.d_all_g);
+        if (sd.d_grouped_g) hipFree(sd.d_grouped_g);
     }
+    for (void *p : b->gather.bufs) hipFree(p);
     if (b->d_counter) hipFree(b->d_counter);
     for (hipStream_t s : b->branch)
         if (s) hipStreamDestroy(s);
@@ -233,6 +353,7 @@ int fei_batch_create(const fei_batch_item *items, int n_items, const fei_options
         std::memset(&d, 0, sizeof d);
         d.form = it.form;
         d.dim = it.mesh.dim;
+        d.key = k;
         d.fp.m = mv;
         d.fp.mu = it.mu;
         d.fp.lam = it.lam;
@@ -337,24 +458,31 @@ int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *ch
         return FEI_OK;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<fei_batch_config> cand;
-    for (int var = 0; var < 2; ++var) {
-        fei_batch_config c{};
-        c.mode = 1;
-        c.variant = var;
-        c.workgroups = 0;
-        c.tiles_per_pop = 1;
-        cand.push_back(c);
-        for (int wg : {1, 2, 4})
-            for (int pop : {1, 4}) {
-                fei_batch_config p{};
-                p.mode = 0;
-                p.variant = var;
-                p.workgroups = wg * b->n_cu;
-                p.tiles_per_pop = pop;
-                cand.push_back(p);
-            }
+    if (adjoint) {
+        int rc = ensure_gather(b);
+        if (rc) return rc;
     }
+    std::vector<fei_batch_config> cand;
+    for (int gather = 0; gather <= adjoint; ++gather)
+        for (int var = 0; var < 2; ++var) {
+            fei_batch_config c{};
+            c.mode = 1;
+            c.variant = var;
+            c.workgroups = 0;
+            c.tiles_per_pop = 1;
+            c.gather = gather;
+            cand.push_back(c);
+            for (int wg : {1, 2, 4})
+                for (int pop : {1, 4}) {
+                    fei_batch_config p{};
+                    p.mode = 0;
+                    p.variant = var;
+                    p.workgroups = wg * b->n_cu;
+                    p.tiles_per_pop = pop;
+                    p.gather = gather;
+                    cand.push_back(p);
+                }
+        }
     hipEvent_t t0, t1;
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
@@ -397,6 +525,14 @@ int fei_batch_set_config(fei_batch *b, int adjoint, const fei_batch_config *cfg)
         return fail(FEI_EINVAL, "mode and variant must be 0 or 1");
     if (cfg->mode == 0 && (cfg->workgroups < 1 || cfg->tiles_per_pop < 1))
         return fail(FEI_EINVAL, "mode 0 needs workgroups >= 1 and tiles_per_pop >= 1");
+    if (cfg->gather != 0 && cfg->gather != 1) return fail(FEI_EINVAL, "gather must be 0 or 1");
+    if (cfg->gather && !adjoint) return fail(FEI_EINVAL, "gather applies to the adjoint only");
+    for (int r : cfg->reserved)
+        if (r) return fail(FEI_EINVAL, "reserved fields must be zero");
+    if (cfg->gather) {
+        int rc = ensure_gather(b);
+        if (rc) return rc;
+    }
     b->side[adjoint].cfg = *cfg;
     return build_graph(b, adjoint);
 }

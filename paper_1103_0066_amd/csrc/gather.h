@@ -1,0 +1,210 @@
+// Vertex gradients without global atomics: the adjoint writes J-bar per
+// element, and one thread per vertex sums the contributions of the elements
+// around it, read through a vertex-to-element incidence (CSR) built once per
+// mesh.  Global atomics execute at the memory side on MI355X (they bypass
+// L2), so for repeated adjoints on one mesh this gather replaces ~3 atomics
+// per distinct vertex of every wave's tile by plain reads of 36 bytes per
+// element and one read-modify-write per vertex.  Incidences are sorted and
+// combined in a fixed order, so the result does not depend on the launch.
+//
+// Contribution of element e to its vertex a (reverse of J = [x_1 - x_0 | ...]):
+// column a - 1 of J-bar for a > 0, minus the sum of its columns for a = 0.
+#pragma once
+
+#include "params.h"
+
+namespace fei {
+
+__global__ __launch_bounds__(256) void incidence_zero_kernel(int32_t *a, int64_t n)
+{
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += gridDim.x * 256ll) a[i] = 0;
+}
+
+// deg[v + 1] = number of incidences of v (ptr[0] stays 0).
+__global__ __launch_bounds__(256) void incidence_count_kernel(Incidence g)
+{
+    const int64_t total = g.n_elements * g.nv;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += gridDim.x * 256ll) {
+        const int32_t v = g.conn[i];
+        if (v >= 0 && v < g.n_vertices) atomicAdd(g.ptr + v + 1, 1);
+    }
+}
+
+// In-place inclusive scan of ptr[0 .. n) by one workgroup: each thread scans a
+// contiguous chunk, the chunk totals are scanned in LDS, then added back.
+__global__ __launch_bounds__(1024) void incidence_scan_kernel(int32_t *ptr, int64_t n)
+{
+    __shared__ int32_t tot[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t b = t * chunk, e = (b + chunk < n) ? b + chunk : n;
+    int32_t run = 0;
+    for (int64_t i = b; i < e; ++i) run += ptr[i];
+    tot[t] = run;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t v = t >= off ? tot[t - off] : 0;
+        __syncthreads();
+        tot[t] += v;
+        __syncthreads();
+    }
+    int32_t acc = t > 0 ? tot[t - 1] : 0;
+    for (int64_t i = b; i < e; ++i) {
+        acc += ptr[i];
+        ptr[i] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void incidence_fill_kernel(Incidence g)
+{
+    const int64_t total = g.n_elements * g.nv;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += gridDim.x * 256ll) {
+        const int32_t v = g.conn[i];
+        if (v >= 0 && v < g.n_vertices) {
+            const int32_t pos = atomicAdd(g.cursor + v, 1);
+            g.inc[g.ptr[v] + pos] = int32_t(i);   // i = e * nv + a
+        }
+    }
+}
+
+// In-place heapsort of a[0 .. n) (O(n log n) for vertices of any degree).
+__device__ inline void heap_sort(int32_t *a, int32_t n)
+{
+    auto sift = [a](int32_t root, int32_t end) {
+        for (;;) {
+            int32_t c = 2 * root + 1;
+            if (c >= end) return;
+            if (c + 1 < end && a[c + 1] > a[c]) ++c;
+            if (a[root] >= a[c]) return;
+            const int32_t t = a[root];
+            a[root] = a[c];
+            a[c] = t;
+            root = c;
+        }
+    };
+    for (int32_t r = n / 2 - 1; r >= 0; --r) sift(r, n);
+    for (int32_t end = n - 1; end > 0; --end) {
+        const int32_t t = a[0];
+        a[0] = a[end];
+        a[end] = t;
+        sift(0, end);
+    }
+}
+
+// Sorts every vertex's incidences: insertion sort for the usual short lists
+// (~24 per vertex on meshes of tets), heapsort beyond 32.
+__global__ __launch_bounds__(256) void incidence_sort_kernel(Incidence g)
+{
+    for (int64_t v = blockIdx.x * 256ll + threadIdx.x; v < g.n_vertices; v += gridDim.x * 256ll) {
+        const int32_t b = g.ptr[v], e = g.ptr[v + 1];
+        if (e - b > 32) {
+            heap_sort(g.inc + b, e - b);
+            continue;
+        }
+        for (int32_t i = b + 1; i < e; ++i) {
+            const int32_t x = g.inc[i];
+            int32_t j = i - 1;
+            while (j >= b && g.inc[j] > x) {
+                g.inc[j + 1] = g.inc[j];
+                --j;
+            }
+            g.inc[j + 1] = x;
+        }
+    }
+}
+
+// Global-memory views of the item's arrays: pointers read from the item table
+// are generic; cast, their loads are plain global loads.
+typedef __attribute__((address_space(1))) const int32_t g_i32;
+typedef __attribute__((address_space(1))) const float g_f32;
+
+// Eight lanes per vertex: lane k of the vertex's group sums incidences
+// k, k + 8, k + 16, ... of its (sorted) list, then the eight partial sums are
+// combined by a fixed butterfly; the order of every addition is fixed by the
+// incidence list alone, so the result does not depend on the launch.
+constexpr int kGatherLanes = 8;
+
+template <int DIM>
+__device__ __forceinline__ void gather_vertex(const GatherItem &it, int64_t v, int k, bool live)
+{
+    constexpr int NV = DIM + 1, NJ = DIM * DIM;
+    const g_i32 *ptr = (const g_i32 *)it.ptr;
+    const g_i32 *inc = (const g_i32 *)it.inc;
+    const g_f32 *jbar = (const g_f32 *)it.jbar;
+    float s[DIM] = {};
+    int32_t b = 0, e = 0;
+    if (live) {
+        b = ptr[v];
+        e = ptr[v + 1];
+    }
+    // up to 4 of the lane's incidences per step: indices, then J-bar rows,
+    // loaded together
+    constexpr int U = 4;
+    for (int32_t j0 = b + k; j0 < e; j0 += U * kGatherLanes) {
+        int32_t idx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t j = j0 + u * kGatherLanes;
+            idx[u] = j < e ? inc[j] : -1;
+        }
+        float Jv[U][NJ];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const g_f32 *J = jbar + int64_t(idx[u] >= 0 ? idx[u] / NV : 0) * NJ;
+#pragma unroll
+            for (int q = 0; q < NJ; ++q) Jv[u][q] = J[q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (idx[u] < 0) break;
+            const int a = idx[u] % NV;
+#pragma unroll
+            for (int al = 0; al < DIM; ++al) {
+                // column a - 1 of J-bar for a > 0, minus the row sum for a = 0
+                // (selected without indexing the register array at run time)
+                float c = 0.f;
+#pragma unroll
+                for (int m = 0; m < DIM; ++m) c += Jv[u][al * DIM + m];
+                c = -c;
+#pragma unroll
+                for (int m = 0; m < DIM; ++m) c = (a == m + 1) ? Jv[u][al * DIM + m] : c;
+                s[al] += c;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < kGatherLanes; off <<= 1)
+#pragma unroll
+        for (int al = 0; al < DIM; ++al) s[al] += __shfl_xor(s[al], off, kGatherLanes);
+    if (!live || k != 0 || b == e) return;
+    float *X[3] = {it.dx, it.dy, it.dz};
+#pragma unroll
+    for (int al = 0; al < DIM; ++al) {
+        if (it.atomic) unsafeAtomicAdd(X[al] + v, s[al]);
+        else X[al][v] += s[al];
+    }
+}
+
+// Thread t works on global vertex t / 8 (every lane of a group takes part in
+// the butterfly, including those past the last vertex).
+__global__ __launch_bounds__(256) void vertex_gather_kernel(const GatherItem *items, int n_items,
+                                                            int64_t n_total)
+{
+    const int64_t t = blockIdx.x * 256ll + threadIdx.x;
+    const int64_t gv = t / kGatherLanes;
+    const int k = int(t % kGatherLanes);
+    const bool live = gv < n_total;
+    const int64_t gq = live ? gv : n_total - 1;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].v_begin <= gq) lo = mid;
+        else hi = mid - 1;
+    }
+    const GatherItem &it = items[lo];
+    const int64_t v = gq - it.v_begin;
+    if (it.dim == 3) gather_vertex<3>(it, v, k, live);
+    else gather_vertex<2>(it, v, k, live);
+}
+
+}  // namespace fei

@@ -2,10 +2,12 @@
 // the host layer dispatches through.  One translation unit, so the
 // device-global reference tables (K fragments, sparse K) exist once per
 // device module.
+#include <algorithm>
 #include <type_traits>
 
 #include "adjoint.h"
 #include "batch_dev.h"
+#include "gather.h"
 #include "fwd_fma.h"
 #include "fwd_mfma.h"
 
@@ -347,6 +349,31 @@ hipError_t launch_batch_group(bool adjoint, int form, int dim, int precision, in
 hipError_t launch_batch_reset(int32_t *counter, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_incidence_build(const Incidence &g, hipStream_t s)
+{
+    auto grid = [](int64_t n) { return unsigned(std::min<int64_t>((n + 255) / 256, 8192)); };
+    const int64_t total = g.n_elements * g.nv;
+    hipLaunchKernelGGL(incidence_zero_kernel, dim3(grid(g.n_vertices + 1)), dim3(256), 0, s, g.ptr,
+                       g.n_vertices + 1);
+    hipLaunchKernelGGL(incidence_zero_kernel, dim3(grid(g.n_vertices)), dim3(256), 0, s, g.cursor,
+                       g.n_vertices);
+    hipLaunchKernelGGL(incidence_count_kernel, dim3(grid(total)), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(incidence_scan_kernel, dim3(1), dim3(1024), 0, s, g.ptr, g.n_vertices + 1);
+    hipLaunchKernelGGL(incidence_fill_kernel, dim3(grid(total)), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(incidence_sort_kernel, dim3(grid(g.n_vertices)), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex_gather(const GatherItem *items, int n_items, int64_t n_total,
+                                hipStream_t s)
+{
+    if (n_total == 0) return hipSuccess;
+    const int64_t threads = n_total * kGatherLanes;
+    hipLaunchKernelGGL(vertex_gather_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s,
+                       items, n_items, n_total);
     return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ struct AdjParams {
     float *dmu, *dlam;         // [E] or NULL
     int32_t *counters;
     float tau2;
+    float *jbar;               // [E][dim][dim]: J-bar per element instead of the
+                               // vertex scatter (gathered per vertex later); NULL: scatter
 };
 
 // Kernel selection key.
@@ -54,6 +56,8 @@ AdjLauncher find_adjoint(const Variant &v);
 struct BatchItemDev {
     int32_t form;        // fei::Form
     int32_t dim;
+    int32_t key;         // index of the item in the caller's list (host bookkeeping)
+    int32_t pad_;
     int64_t tile_begin;  // first global tile (256 elements) of this item
     FwdParams fp;
     AdjParams ap;
@@ -79,6 +83,35 @@ hipError_t launch_batch_group(bool adjoint, int form, int dim, int precision, in
 
 // Device-side connectivity check: writes the count of entries outside
 // [0, n_vertices) into *n_bad_dev (int64, zeroed by the kernel's caller).
+// Vertex-to-element incidence of one mesh (CSR, rows = vertices, entries
+// e * (dim + 1) + a in increasing order) and the per-vertex gather of J-bar.
+struct Incidence {
+    const int32_t *conn;       // [E][nv]
+    int64_t n_elements;
+    int64_t n_vertices;
+    int32_t nv;                // dim + 1
+    int32_t *ptr;              // [n_vertices + 1]
+    int32_t *inc;              // [n_elements * nv]
+    int32_t *cursor;           // [n_vertices] scratch
+};
+// Builds ptr and inc on stream s (entries with a vertex outside [0, n_vertices)
+// are left out).
+hipError_t launch_incidence_build(const Incidence &g, hipStream_t s);
+
+struct GatherItem {
+    const int32_t *ptr, *inc;  // incidence of the item's mesh
+    const float *jbar;         // [E][dim][dim]
+    float *dx, *dy, *dz;       // accumulated
+    int64_t v_begin;           // first global vertex of the item
+    int64_t n_vertices;
+    int32_t dim;
+    int32_t atomic;            // 1 if another item accumulates into the same arrays
+};
+// Eight threads per vertex of every item: dx[v] += sum over the vertex's
+// incidences, combined in an order fixed by the sorted incidence list.
+hipError_t launch_vertex_gather(const GatherItem *items, int n_items, int64_t n_total,
+                                hipStream_t s);
+
 hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad_dev,
                            hipStream_t s);
 

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_status_strings():
     lib = _lib.load()
-    assert lib.fei_abi_version() == 1
+    assert lib.fei_abi_version() == _lib.ABI_VERSION == 2
     for s in (0, -1, -2, -3, -4):
         assert lib.fei_status_str(s)
     assert lib.fei_status_str(-99) == b"unknown status"

@@ -80,11 +80,16 @@ def test_batch_forward_matches_per_mesh_launches(precision):
     b.close()
 
 
+# the adjoint also in vertex-gather form (J-bar per element, one thread per vertex)
+ADJ_CONFIGS = CONFIGS + [dict(c, gather=1) for c in CONFIGS]
+
+
 def test_batch_adjoint_matches_oracle():
     items, host = _items(with_adjoint=True)
     b = fei.Batch(items)
-    for cfg in CONFIGS:
+    for cfg in ADJ_CONFIGS:
         b.set_config(cfg, adjoint=True)
+        assert b.config(adjoint=True)["gather"] == cfg.get("gather", 0)
         for it in items:
             it["dcoords"].zero_()
         torch.cuda.synchronize()
@@ -108,6 +113,70 @@ def test_batch_adjoint_matches_oracle():
     b.close()
 
 
+def test_batch_adjoint_gather_is_deterministic_and_matches_scatter():
+    """The vertex gather sums in element order: bitwise the same on every run and
+    in every graph shape; the atomic scatter agrees within the atomic tolerance."""
+    items, host = _items(with_adjoint=True)
+    b = fei.Batch(items)
+    runs = []
+    for cfg in [dict(c, gather=1) for c in CONFIGS] + [CONFIGS[0]]:
+        b.set_config(cfg, adjoint=True)
+        for rep in range(2):
+            for it in items:
+                it["dcoords"].zero_()
+            torch.cuda.synchronize()
+            b.run_adjoint()
+            torch.cuda.synchronize()
+            runs.append([it["dcoords"].cpu().numpy().copy() for it in items])
+    ref = runs[0]
+    for r in runs[1:-2]:
+        for k in range(len(items)):
+            assert np.array_equal(r[k].view(np.uint32), ref[k].view(np.uint32)), k
+    for (form, m, mu, lam), it, g_sc, g_ga in zip(host, items, runs[-1], ref):
+        if m.n_elements == 0:
+            continue
+        gv, _, _, _ = oracle.gradient(form, m.coords, m.conn, it["dA"].cpu().numpy(), mu, lam)
+        sc = vertex_scale(gv, m.conn, m.n_vertices)
+        used = sc > 0
+        assert (np.abs(g_sc - g_ga).T.max(axis=1)[used] / sc[used]).max() <= TOL_VERTEX
+    b.close()
+
+
+def test_batch_adjoint_gather_with_shared_gradient_arrays():
+    """Two items of one mesh accumulating into the same dcoords: the gather then
+    adds atomically, and the sum is that of both items."""
+    m = meshgen.flatten_elements(meshgen.cube_mesh(5, 4, 4, 0.15, 91), 5, 92)
+    mu, lam = meshgen.lame(m.n_elements, 93)
+    coords, conn = torch.from_numpy(m.soa()).to(DEV), torch.from_numpy(m.conn).to(DEV)
+    dc = torch.zeros((3, m.n_vertices), dtype=torch.float32, device=DEV)
+    dAs = [meshgen.upstream(m.n_elements, 12, 94 + k) for k in range(2)]
+    items = [{"form": "elastic_p1", "coords": coords, "conn": conn,
+              "mu": torch.from_numpy(mu).to(DEV), "lam": torch.from_numpy(lam).to(DEV),
+              "dA": torch.from_numpy(dA).to(DEV), "dcoords": dc} for dA in dAs]
+    b = fei.Batch(items)
+    b.set_config({"mode": 1, "variant": 0, "gather": 1}, adjoint=True)
+    b.run_adjoint()
+    torch.cuda.synchronize()
+    gv = sum(oracle.gradient("elastic_p1", m.coords, m.conn, dA, mu, lam)[0] for dA in dAs)
+    go = oracle.vertex_gradient(gv, m.conn, m.n_vertices)
+    sc = sum(vertex_scale(oracle.gradient("elastic_p1", m.coords, m.conn, dA, mu, lam)[0],
+                          m.conn, m.n_vertices) for dA in dAs)
+    g = dc.cpu().numpy().T
+    used = sc > 0
+    assert (np.abs(g - go).max(axis=1)[used] / sc[used]).max() <= TOL_VERTEX
+    b.close()
+
+
+def test_batch_gather_config_is_validated():
+    items, _ = _items(with_adjoint=True)
+    b = fei.Batch(items)
+    with pytest.raises(fei.FeiError):
+        b.set_config({"mode": 1, "variant": 0, "gather": 1})          # forward side
+    with pytest.raises(fei.FeiError):
+        b.set_config({"mode": 1, "variant": 0, "gather": 2}, adjoint=True)
+    b.close()
+
+
 def test_batch_tune_picks_a_working_configuration():
     items, host = _items(with_adjoint=True)
     eager = [fei.integrate(it["coords"], it["conn"], it["form"], it.get("mu"),
@@ -123,7 +192,8 @@ def test_batch_tune_picks_a_working_configuration():
     for k, it in enumerate(items):
         assert np.array_equal(it["A"].cpu().numpy().view(np.uint32), eager[k].view(np.uint32))
     acfg = b.tune(adjoint=True)
-    assert acfg["ms"] > 0
+    assert acfg["ms"] > 0 and acfg["gather"] in (0, 1)
+    assert b.config(adjoint=True) == acfg
     b.close()
 
 
