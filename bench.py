@@ -248,6 +248,18 @@ def main():
         gbs = ab / (r["kernel_ms_mean"] * 1e-3) / 1e9
         legs["adjoint_fp32"] = dict(r, gbs=gbs, frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=ab,
                                     elements_per_s=E / (r["kernel_ms_mean"] * 1e-3))
+        # the same adjoint through a one-mesh plan (tuned: atomic scatter or vertex gather)
+        plan = fei.Batch([{"form": "elastic_p1", "coords": coords, "conn": conn, "mu": mu,
+                           "lam": lam, "A": A, "dA": dA, "dcoords": dc, "dmu": dmu,
+                           "dlam": dlam}])
+        cfg = plan.tune(adjoint=True)
+        r = time_leg(plan.run_adjoint, args.steps, args.warmup, "adjoint_plan_fp32")
+        gbs = ab / (r["kernel_ms_mean"] * 1e-3) / 1e9
+        legs["adjoint_plan_fp32"] = dict(
+            r, gbs=gbs, frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=ab, tuned_config=cfg,
+            elements_per_s=E / (r["kernel_ms_mean"] * 1e-3),
+            note="one hipGraphLaunch per step (adjoint kernel, then the vertex gather when chosen)")
+        plan.close()
         # 3D P1 Laplacian on the unflattened cube
         wl = meshgen.lap3d(args.n)
         cl = torch.from_numpy(wl.mesh.soa()).to(dev)
@@ -262,6 +274,23 @@ def main():
                 r, gbs=gbs, frac=gbs / HBM_PEAK_GBS, algorithmic_bytes=lb,
                 elements_per_s=wl.mesh.n_elements / (r["kernel_ms_mean"] * 1e-3),
                 note="129 MB working set fits the 256 MB MALL: GB/s here is not HBM-only")
+        # 3D P1 Laplacian adjoint: single call (atomic scatter) and one-mesh plan
+        dAl = torch.from_numpy(meshgen.upstream(wl.mesh.n_elements, 4, 1104)).to(dev)
+        dcl = torch.zeros((3, wl.mesh.n_vertices), dtype=torch.float32, device=dev)
+        lab = adjoint_bytes(wl.mesh.n_elements, wl.mesh.n_vertices, 4, 3, False)
+        r = time_leg(lambda: fei.integrate_adjoint(cl, kl, "laplace_p1", dAl, dcoords=dcl),
+                     args.steps, args.warmup, "laplace3d_adjoint_fp32")
+        gbs = lab / (r["kernel_ms_mean"] * 1e-3) / 1e9
+        legs["laplace3d_adjoint_fp32"] = dict(r, gbs=gbs, frac=gbs / HBM_PEAK_GBS,
+                                              algorithmic_bytes=lab)
+        plan = fei.Batch([{"form": "laplace_p1", "coords": cl, "conn": kl, "A": Al, "dA": dAl,
+                           "dcoords": dcl}])
+        cfg = plan.tune(adjoint=True)
+        r = time_leg(plan.run_adjoint, args.steps, args.warmup, "laplace3d_adjoint_plan_fp32")
+        gbs = lab / (r["kernel_ms_mean"] * 1e-3) / 1e9
+        legs["laplace3d_adjoint_plan_fp32"] = dict(r, gbs=gbs, frac=gbs / HBM_PEAK_GBS,
+                                                   algorithmic_bytes=lab, tuned_config=cfg)
+        plan.close()
         del Al
         # 3D P2 Laplacian on the same unflattened cube (10 x 10 matrices)
         A2 = torch.empty((wl.mesh.n_elements, 10, 10), dtype=torch.float32, device=dev)
