@@ -191,7 +191,9 @@ int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream);
  *      work counter (reset by a kernel node) until none are left;
  *   1  one kernel per (form, dim) group, the groups captured as concurrent
  *      branches of the graph (each kernel has the registers and LDS of its
- *      own form only).
+ *      own form only);
+ *   2  the single-mesh kernels of fei_integrate / fei_integrate_adjoint, one
+ *      launch per item, the items of a group in turn on the group's branch.
  * fei_batch_tune times candidate configurations on the caller's data and
  * rebuilds the graph with the fastest.
  * The plan owns its descriptor tables, work counter, streams and graphs, and
@@ -211,8 +213,9 @@ typedef struct fei_batch_item {
 } fei_batch_item;
 
 typedef struct fei_batch_config {
-    int32_t mode;           /* 0: persistent multi-form kernel, 1: per-group kernels */
-    int32_t variant;        /* output staging: 0 wide (LDS <= 64 KB per form), 1 narrow */
+    int32_t mode;           /* 0: persistent multi-form kernel, 1: per-group kernels,
+                               2: single-mesh kernels per item */
+    int32_t variant;        /* modes 0, 1: output staging, 0 wide, 1 narrow */
     int32_t workgroups;     /* mode 0: persistent workgroups launched */
     int32_t tiles_per_pop;  /* mode 0: tiles taken from the counter per atomic */
     float ms;               /* measured time of this configuration (0: not tuned) */
@@ -222,8 +225,8 @@ typedef struct fei_batch_config {
                                plan buffer, then each vertex sums its
                                elements' terms in an order fixed by the mesh --
                                no atomics (unless two items share gradient
-                               arrays), and the result does not depend on the
-                               launch.  Setting 1 first builds the plan's
+                               arrays), and every run of the graph gives the
+                               same bits.  Setting 1 first builds the plan's
                                vertex-to-element incidence from the items'
                                connectivity (device-synchronizing; the plan
                                then holds 4 (N_v + 1) + 4 (d + 1) E + 4 d^2 E

@@ -143,13 +143,23 @@ hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t
             const Group &G = sd.groups[g];
             hipStream_t bs = b->branch[g];
             if ((e = hipStreamWaitEvent(bs, b->fork, 0)) != hipSuccess) return e;
-            if (adj && G.n == 1) {
-                // a group of one mesh: the single-mesh adjoint (persistent,
-                // with cross-tile prefetch) on that item's parameters
-                const BatchItemDev &d = gather ? sd.grouped_g[G.off] : sd.grouped[G.off];
-                const AdjLauncher run = find_adjoint(Variant{d.form, d.dim, 0, P_FP32, 0});
-                if (!run) return hipErrorInvalidValue;
-                if ((e = run(d.ap, bs)) != hipSuccess) return e;
+            if (c.mode == 2 || (adj && G.n == 1)) {
+                // the single-mesh kernels, one launch per item of the group in
+                // turn (a group of one mesh always runs the adjoint this way:
+                // persistent, with cross-tile prefetch)
+                for (int k = 0; k < G.n; ++k) {
+                    const BatchItemDev &d = gather ? sd.grouped_g[G.off + k] : sd.grouped[G.off + k];
+                    const Variant v{d.form, d.dim, 0, prec, 0};
+                    if (adj) {
+                        const AdjLauncher run = find_adjoint(v);
+                        if (!run) return hipErrorInvalidValue;
+                        if ((e = run(d.ap, bs)) != hipSuccess) return e;
+                    } else {
+                        const FwdLauncher run = find_forward(v);
+                        if (!run) return hipErrorInvalidValue;
+                        if ((e = run(d.fp, bs)) != hipSuccess) return e;
+                    }
+                }
             } else {
                 BatchLaunch L{grouped + G.off, G.n, 1, G.tiles, nullptr};
                 if ((e = launch_batch_group(adj != 0, G.form, G.dim, prec, c.variant, L, bs)) !=
@@ -472,6 +482,11 @@ int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *ch
             c.tiles_per_pop = 1;
             c.gather = gather;
             cand.push_back(c);
+            if (var == 0) {
+                fei_batch_config m2 = c;
+                m2.mode = 2;
+                cand.push_back(m2);
+            }
             for (int wg : {1, 2, 4})
                 for (int pop : {1, 4}) {
                     fei_batch_config p{};
@@ -521,8 +536,8 @@ int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *ch
 int fei_batch_set_config(fei_batch *b, int adjoint, const fei_batch_config *cfg)
 {
     if (!b || !cfg || (adjoint != 0 && adjoint != 1)) return fail(FEI_EINVAL, "bad argument");
-    if ((cfg->mode != 0 && cfg->mode != 1) || (cfg->variant != 0 && cfg->variant != 1))
-        return fail(FEI_EINVAL, "mode and variant must be 0 or 1");
+    if ((cfg->mode < 0 || cfg->mode > 2) || (cfg->variant != 0 && cfg->variant != 1))
+        return fail(FEI_EINVAL, "mode must be 0, 1 or 2 and variant 0 or 1");
     if (cfg->mode == 0 && (cfg->workgroups < 1 || cfg->tiles_per_pop < 1))
         return fail(FEI_EINVAL, "mode 0 needs workgroups >= 1 and tiles_per_pop >= 1");
     if (cfg->gather != 0 && cfg->gather != 1) return fail(FEI_EINVAL, "gather must be 0 or 1");

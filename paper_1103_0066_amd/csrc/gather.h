@@ -5,7 +5,7 @@
 // L2), so for repeated adjoints on one mesh this gather replaces ~3 atomics
 // per distinct vertex of every wave's tile by plain reads of 36 bytes per
 // element and one read-modify-write per vertex.  Incidences are sorted and
-// combined in a fixed order, so the result does not depend on the launch.
+// combined in a fixed order, so every run gives the same bits.
 //
 // Contribution of element e to its vertex a (reverse of J = [x_1 - x_0 | ...]):
 // column a - 1 of J-bar for a > 0, minus the sum of its columns for a = 0.

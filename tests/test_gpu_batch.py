@@ -53,7 +53,8 @@ def _items(seed=0, with_adjoint=False):
 CONFIGS = [{"mode": 1, "variant": 0}, {"mode": 1, "variant": 1},
            {"mode": 0, "variant": 0, "workgroups": 256, "tiles_per_pop": 1},
            {"mode": 0, "variant": 1, "workgroups": 512, "tiles_per_pop": 4},
-           {"mode": 0, "variant": 0, "workgroups": 3, "tiles_per_pop": 2}]
+           {"mode": 0, "variant": 0, "workgroups": 3, "tiles_per_pop": 2},
+           {"mode": 2, "variant": 0}]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16x2", "bf16x3"])
@@ -114,31 +115,37 @@ def test_batch_adjoint_matches_oracle():
 
 
 def test_batch_adjoint_gather_is_deterministic_and_matches_scatter():
-    """The vertex gather sums in element order: bitwise the same on every run and
-    in every graph shape; the atomic scatter agrees within the atomic tolerance."""
+    """The vertex gather sums in an order fixed by the mesh: every run of a graph
+    gives the same bits (graph shapes whose kernels differ may differ in the last
+    bits of J-bar), and all shapes, and the atomic scatter, agree within the
+    atomic tolerance."""
     items, host = _items(with_adjoint=True)
     b = fei.Batch(items)
     runs = []
     for cfg in [dict(c, gather=1) for c in CONFIGS] + [CONFIGS[0]]:
         b.set_config(cfg, adjoint=True)
-        for rep in range(2):
+        reps = []
+        for rep in range(3):
             for it in items:
                 it["dcoords"].zero_()
             torch.cuda.synchronize()
             b.run_adjoint()
             torch.cuda.synchronize()
-            runs.append([it["dcoords"].cpu().numpy().copy() for it in items])
+            reps.append([it["dcoords"].cpu().numpy().copy() for it in items])
+        if cfg.get("gather"):
+            for r in reps[1:]:
+                for k in range(len(items)):
+                    assert np.array_equal(r[k].view(np.uint32), reps[0][k].view(np.uint32)), (cfg, k)
+        runs.append(reps[0])
     ref = runs[0]
-    for r in runs[1:-2]:
-        for k in range(len(items)):
-            assert np.array_equal(r[k].view(np.uint32), ref[k].view(np.uint32)), k
-    for (form, m, mu, lam), it, g_sc, g_ga in zip(host, items, runs[-1], ref):
-        if m.n_elements == 0:
-            continue
-        gv, _, _, _ = oracle.gradient(form, m.coords, m.conn, it["dA"].cpu().numpy(), mu, lam)
-        sc = vertex_scale(gv, m.conn, m.n_vertices)
-        used = sc > 0
-        assert (np.abs(g_sc - g_ga).T.max(axis=1)[used] / sc[used]).max() <= TOL_VERTEX
+    for r in runs[1:]:
+        for (form, m, mu, lam), it, g, g0 in zip(host, items, r, ref):
+            if m.n_elements == 0:
+                continue
+            gv, _, _, _ = oracle.gradient(form, m.coords, m.conn, it["dA"].cpu().numpy(), mu, lam)
+            sc = vertex_scale(gv, m.conn, m.n_vertices)
+            used = sc > 0
+            assert (np.abs(g - g0).T.max(axis=1)[used] / sc[used]).max() <= TOL_VERTEX
     b.close()
 
 
