@@ -256,7 +256,9 @@ __device__ __forceinline__ void scatter_vertices(const AdjParams &p, const int (
     }
 }
 
-template <int FORM, int DIM, typename CT, int R>
+// GATHER: the tile always writes J-bar (AdjParams.jbar) and carries no vertex
+// table; otherwise it scatters, or writes J-bar when jbar is set.
+template <int FORM, int DIM, typename CT, int R, bool GATHER = false>
 struct AdjTile {
     using T = Traits<FORM, DIM>;
     using S = Stage<FORM, DIM, R>;
@@ -269,10 +271,11 @@ struct AdjTile {
     static constexpr int NSTASH = (R > 0 && sizeof(CT) == 4) ? 2 : 0;
     // LDS: dA staging | FP64 fold of a flagged element | vertex-merge keys |
     // values | stashed dA of flagged elements
+    static constexpr int SLOTS = GATHER ? 0 : kHashSlots;
     static constexpr int OFF_U64 = 4 * SW * 4;
     static constexpr int OFF_KEY = OFF_U64 + 4 * GP * 8;
-    static constexpr int OFF_VAL = OFF_KEY + 4 * kHashSlots * 4;
-    static constexpr int OFF_STASH = OFF_VAL + 4 * kHashSlots * DIM * 4;
+    static constexpr int OFF_VAL = OFF_KEY + 4 * SLOTS * 4;
+    static constexpr int OFF_STASH = OFF_VAL + 4 * SLOTS * DIM * 4;
     static constexpr int LDS_BYTES = OFF_STASH + 4 * NSTASH * NN * 4;
 
     struct Lds {
@@ -287,8 +290,8 @@ struct AdjTile {
         const int wave = wave_id();
         return {reinterpret_cast<float *>(smem) + wave * SW,
                 reinterpret_cast<double *>(smem + OFF_U64) + wave * GP,
-                reinterpret_cast<int *>(smem + OFF_KEY) + wave * kHashSlots,
-                reinterpret_cast<float *>(smem + OFF_VAL) + wave * kHashSlots * DIM,
+                reinterpret_cast<int *>(smem + OFF_KEY) + wave * SLOTS,
+                reinterpret_cast<float *>(smem + OFF_VAL) + wave * SLOTS * DIM,
                 reinterpret_cast<float *>(smem + OFF_STASH) + wave * NSTASH * NN};
     }
 
@@ -487,7 +490,7 @@ struct AdjTile {
             if (valid && p.dmu) p.dmu[e] = o.mubar;
             if (valid && p.dlam) p.dlam[e] = o.lambar;
         }
-        if (p.jbar) {
+        if (GATHER || p.jbar) {
             // J-bar per element, gathered per vertex by a later kernel.  A full
             // wave's 64 blocks of DIM^2 floats are one contiguous run: staged
             // in LDS and stored as 16-byte pieces; otherwise lane by lane.
@@ -511,7 +514,7 @@ struct AdjTile {
 #pragma unroll
                     for (int m = 0; m < DIM; ++m) J[al * DIM + m] = o.Jbar[al][m];
             }
-        } else {
+        } else if constexpr (!GATHER) {
             scatter_vertices<DIM>(p, in.v, o.Jbar, valid, L.key, L.val, lane);
         }
     }
@@ -550,10 +553,14 @@ struct AdjTile {
 // after the reverse pass, before this tile's atomics.  Vector-memory
 // operations complete in issue order, so every prefetch is issued before the
 // stores and atomics of the step it overlaps.
-template <int FORM, int DIM, typename CT, int R>
-__global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p, int64_t n_tiles)
+// Without the vertex table the gather form fits two workgroups per CU in LDS;
+// asking for two waves per SIMD keeps it within 256 registers (measured 4%
+// faster despite a 12-byte spill).
+template <int FORM, int DIM, typename CT, int R, bool GATHER>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GATHER ? 2 : 1)))
+void adj_fma_kernel(AdjParams p, int64_t n_tiles)
 {
-    using Tile = AdjTile<FORM, DIM, CT, R>;
+    using Tile = AdjTile<FORM, DIM, CT, R, GATHER>;
     using AccT = typename Tile::AccT;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
     const PersistentTiles pt(n_tiles);

@@ -149,7 +149,7 @@ hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t
                 // persistent, with cross-tile prefetch)
                 for (int k = 0; k < G.n; ++k) {
                     const BatchItemDev &d = gather ? sd.grouped_g[G.off + k] : sd.grouped[G.off + k];
-                    const Variant v{d.form, d.dim, 0, prec, 0};
+                    const Variant v{d.form, d.dim, 0, prec, 0, gather ? 1 : 0};
                     if (adj) {
                         const AdjLauncher run = find_adjoint(v);
                         if (!run) return hipErrorInvalidValue;

@@ -73,10 +73,10 @@ hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
     }
 }
 
-template <int F, int D, typename CT, int R>
+template <int F, int D, typename CT, int R, bool GATHER = false>
 hipError_t launch_adj_fma(const AdjParams &p, hipStream_t s)
 {
-    return launch_persistent<adj_fma_kernel<F, D, CT, R>>(p, s);
+    return launch_persistent<adj_fma_kernel<F, D, CT, R, GATHER>>(p, s);
 }
 
 // Staging rows R that fit: R divides n, R*n floats is a whole number of
@@ -184,6 +184,10 @@ template <int F, int D>
 AdjLauncher adj_for_coords(const Variant &v)
 {
     if (v.precision != P_FP32) return nullptr;
+    if (v.gather) {   // plans' vertex gather: FP32 coordinates, default staging
+        if (v.coord_f64 || v.rows != 0) return nullptr;
+        return &launch_adj_fma<F, D, float, default_adj_rows<F, D>(), true>;
+    }
     return v.coord_f64 ? adj_fma_rows<F, D, double>(v.rows) : adj_fma_rows<F, D, float>(v.rows);
 }
 

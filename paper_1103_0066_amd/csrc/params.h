@@ -42,6 +42,7 @@ struct Variant {
     int coord_f64;  // 0/1
     int precision;  // fei_precision
     int rows;       // fei_options.store_rows: 0 default, -1 direct, R > 0 staged
+    int gather;     // adjoint: 1 writes J-bar (AdjParams.jbar) and has no vertex scatter
 };
 
 using FwdLauncher = hipError_t (*)(const FwdParams &, hipStream_t);
