@@ -162,8 +162,8 @@ hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t
                 }
             } else {
                 BatchLaunch L{grouped + G.off, G.n, 1, G.tiles, nullptr};
-                if ((e = launch_batch_group(adj != 0, G.form, G.dim, prec, c.variant, L, bs)) !=
-                    hipSuccess)
+                if ((e = launch_batch_group(adj != 0, gather, G.form, G.dim, prec, c.variant, L,
+                                            bs)) != hipSuccess)
                     return e;
             }
             if ((e = hipEventRecord(b->join[g], bs)) != hipSuccess) return e;

@@ -49,9 +49,9 @@ struct BatchFwdTile {
     }
 };
 
-template <int F, int D, int VAR>
+template <int F, int D, int VAR, bool GATHER = false>
 struct BatchAdjTile {
-    using Tile = AdjTile<F, D, float, batch_adj_rows<F, D, VAR>()>;
+    using Tile = AdjTile<F, D, float, batch_adj_rows<F, D, VAR>(), GATHER>;
     static constexpr int LDS_BYTES = Tile::LDS_BYTES;
 };
 
@@ -160,12 +160,12 @@ __global__ __launch_bounds__(256) void batch_adj_kernel(BatchLaunch b)
 // One (form, dim) group of a batch as an ordinary grid: workgroup b takes
 // the group's tile b.  Specialized per form, so registers and LDS are those
 // of that form alone; the plan captures the groups as concurrent branches of
-// one graph.
-template <int F, int D, int PREC, int VAR, bool ADJ>
+// one graph.  GATHER: the adjoint writes J-bar and has no vertex table.
+template <int F, int D, int PREC, int VAR, bool ADJ, bool GATHER = false>
 __global__ __launch_bounds__(256) void batch_group_kernel(BatchLaunch b)
 {
     using FT = BatchFwdTile<F, D, PREC, VAR>;
-    using AT = typename BatchAdjTile<F, D, VAR>::Tile;
+    using AT = typename BatchAdjTile<F, D, VAR, GATHER>::Tile;
     constexpr int LDS = ADJ ? AT::LDS_BYTES : FT::LDS_BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char smem[LDS > 16 ? LDS : 16];
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);

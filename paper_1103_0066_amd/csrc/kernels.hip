@@ -301,51 +301,57 @@ hipError_t launch_batch(bool adjoint, int precision, int variant, const BatchLau
 
 namespace {
 
-template <int F, int D, int PREC, int VAR, bool ADJ>
+template <int F, int D, int PREC, int VAR, bool ADJ, bool GATHER = false>
 hipError_t launch_group(const BatchLaunch &b, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_group_kernel<F, D, PREC, VAR, ADJ>), dim3(unsigned(b.n_tiles)),
+    hipLaunchKernelGGL((batch_group_kernel<F, D, PREC, VAR, ADJ, GATHER>), dim3(unsigned(b.n_tiles)),
                        dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 
 template <int F, int D, int PREC>
-hipError_t launch_group_pv(bool adj, int variant, const BatchLaunch &b, hipStream_t s)
+hipError_t launch_group_pv(bool adj, bool gather, int variant, const BatchLaunch &b, hipStream_t s)
 {
     if (adj) {
-        if constexpr (PREC == P_FP32)
+        if constexpr (PREC == P_FP32) {
+            if (gather)
+                return variant ? launch_group<F, D, P_FP32, 1, true, true>(b, s)
+                               : launch_group<F, D, P_FP32, 0, true, true>(b, s);
             return variant ? launch_group<F, D, P_FP32, 1, true>(b, s)
                            : launch_group<F, D, P_FP32, 0, true>(b, s);
-        else return hipErrorInvalidValue;
+        } else {
+            return hipErrorInvalidValue;
+        }
     }
     return variant ? launch_group<F, D, PREC, 1, false>(b, s) : launch_group<F, D, PREC, 0, false>(b, s);
 }
 
 template <int F, int D>
-hipError_t launch_group_fd(bool adj, int precision, int variant, const BatchLaunch &b, hipStream_t s)
+hipError_t launch_group_fd(bool adj, bool gather, int precision, int variant, const BatchLaunch &b,
+                           hipStream_t s)
 {
     switch (precision) {
-    case P_FP32: return launch_group_pv<F, D, P_FP32>(adj, variant, b, s);
-    case P_FP16X2: return launch_group_pv<F, D, P_FP16X2>(adj, variant, b, s);
-    case P_BF16X2: return launch_group_pv<F, D, P_BF16X2>(adj, variant, b, s);
-    case P_BF16X3: return launch_group_pv<F, D, P_BF16X3>(adj, variant, b, s);
+    case P_FP32: return launch_group_pv<F, D, P_FP32>(adj, gather, variant, b, s);
+    case P_FP16X2: return launch_group_pv<F, D, P_FP16X2>(adj, gather, variant, b, s);
+    case P_BF16X2: return launch_group_pv<F, D, P_BF16X2>(adj, gather, variant, b, s);
+    case P_BF16X3: return launch_group_pv<F, D, P_BF16X3>(adj, gather, variant, b, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_batch_group(bool adjoint, int form, int dim, int precision, int variant,
-                              const BatchLaunch &b, hipStream_t s)
+hipError_t launch_batch_group(bool adjoint, bool gather, int form, int dim, int precision,
+                              int variant, const BatchLaunch &b, hipStream_t s)
 {
     if (b.n_tiles <= 0) return hipSuccess;
     switch (form * 4 + dim) {
-    case LAP1 * 4 + 2: return launch_group_fd<LAP1, 2>(adjoint, precision, variant, b, s);
-    case LAP1 * 4 + 3: return launch_group_fd<LAP1, 3>(adjoint, precision, variant, b, s);
-    case ELA1 * 4 + 2: return launch_group_fd<ELA1, 2>(adjoint, precision, variant, b, s);
-    case ELA1 * 4 + 3: return launch_group_fd<ELA1, 3>(adjoint, precision, variant, b, s);
-    case LAP2 * 4 + 2: return launch_group_fd<LAP2, 2>(adjoint, precision, variant, b, s);
-    case LAP2 * 4 + 3: return launch_group_fd<LAP2, 3>(adjoint, precision, variant, b, s);
+    case LAP1 * 4 + 2: return launch_group_fd<LAP1, 2>(adjoint, gather, precision, variant, b, s);
+    case LAP1 * 4 + 3: return launch_group_fd<LAP1, 3>(adjoint, gather, precision, variant, b, s);
+    case ELA1 * 4 + 2: return launch_group_fd<ELA1, 2>(adjoint, gather, precision, variant, b, s);
+    case ELA1 * 4 + 3: return launch_group_fd<ELA1, 3>(adjoint, gather, precision, variant, b, s);
+    case LAP2 * 4 + 2: return launch_group_fd<LAP2, 2>(adjoint, gather, precision, variant, b, s);
+    case LAP2 * 4 + 3: return launch_group_fd<LAP2, 3>(adjoint, gather, precision, variant, b, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -79,8 +79,8 @@ hipError_t launch_batch(bool adjoint, int precision, int variant, const BatchLau
 hipError_t launch_batch_reset(int32_t *counter, hipStream_t s);
 // One (form, dim) group of a batch: b.items holds only that group's items and
 // b.n_tiles its tiles (one workgroup per tile).
-hipError_t launch_batch_group(bool adjoint, int form, int dim, int precision, int variant,
-                              const BatchLaunch &b, hipStream_t s);
+hipError_t launch_batch_group(bool adjoint, bool gather, int form, int dim, int precision,
+                              int variant, const BatchLaunch &b, hipStream_t s);
 
 // Device-side connectivity check: writes the count of entries outside
 // [0, n_vertices) into *n_bad_dev (int64, zeroed by the kernel's caller).
