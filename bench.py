@@ -63,13 +63,41 @@ def stored_traffic(kernel_tag: str):
         return None
 
 
+MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense FP16/BF16 MFMA, vendor figure
+
+
+def stored_mfma() -> dict:
+    """MFMA flops per launch and busy fraction per precision from
+    profiles/mfma_elastic_p1_3d_fwd.txt, if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "mfma_elastic_p1_3d_fwd.txt")
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != kernel_source_digest():
+        return {}
+    out = {}
+    for prec in ("fp16x2", "bf16x2", "bf16x3"):
+        try:
+            out[prec] = {"flops": float(vals[f"{prec}_mfma_flops_per_launch"]),
+                         "busy": float(vals[f"{prec}_mfma_busy_fraction"])}
+        except (KeyError, ValueError):
+            pass
+    return out
+
+
 def parse_args():
     p = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--n", type=int, default=64, help="cells per side of the cube")
-    p.add_argument("--legs", default="all", help="'all' or 'fp32' (headline only)")
+    p.add_argument("--legs", default="all",
+                   help="'all', 'forward' (the FP32 and MFMA forward legs) or 'fp32' (headline only)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-ref", action="store_true",
                    help="also run a plain 512 MiB device copy (reference for PMC byte counters)")
@@ -225,16 +253,25 @@ def main():
     }
     legs = {"fp32": dict(head, gbs=achieved, elements_per_s=E / (head["kernel_ms_mean"] * 1e-3))}
     outputs = {}
-    if args.legs == "all":
+    if args.legs in ("all", "forward"):
         outputs["fp32"] = A[:].cpu().numpy() if not args.no_cpu_baseline else None
+        mfma = stored_mfma()
         for prec in ("fp16x2", "bf16x2", "bf16x3"):
             r = time_leg(fwd(prec), args.steps, args.warmup, prec)
             gbs = fwd_bytes / (r["kernel_ms_mean"] * 1e-3) / 1e9
             legs[prec] = dict(r, gbs=gbs, frac=gbs / HBM_PEAK_GBS,
                               elements_per_s=E / (r["kernel_ms_mean"] * 1e-3),
                               speedup_vs_fp32=head["kernel_ms_mean"] / r["kernel_ms_mean"])
+            if prec in mfma:
+                fl = mfma[prec]["flops"]
+                legs[prec]["mfma"] = {
+                    "flops_per_launch": fl,
+                    "achieved_tflops": fl / (r["kernel_ms_mean"] * 1e-3) / 1e12,
+                    "peak_tflops": MFMA_PEAK_TFLOPS, "busy_fraction": mfma[prec]["busy"],
+                    "source": "profiles/mfma_elastic_p1_3d_fwd.txt"}
             if not args.no_cpu_baseline:
                 outputs[prec] = A.cpu().numpy()
+    if args.legs == "all":
         # adjoint of the same workload
         dA = torch.from_numpy(w.dA).to(dev)
         dc = torch.zeros((3, Nv), dtype=torch.float32, device=dev)
