@@ -123,6 +123,13 @@ struct MfmaTile {
     using S = MfmaShape<FORM, DIM, PREC>;
     using L = MfmaLds<FORM, DIM, PREC>;
     static constexpr int FRAG_BYTES = L::AREG ? 0 : S::NFRAG * 16;
+    // non-temporal stores for the 576-byte elasticity matrices only, as in
+    // the FP32 form
+    __device__ static void put(f32x4_t *dst, f32x4_t v)
+    {
+        if constexpr (T::N >= 12) store_out(dst, v);
+        else *dst = v;
+    }
     static constexpr int LDS_BYTES = FRAG_BYTES + 4 * L::WBYTES + 256 * 4;
 
     struct Frags {
@@ -226,7 +233,7 @@ struct MfmaTile {
                     float *Ae = p.A + e * (int64_t)S::NN;
                     if constexpr (S::NN % 4 == 0) {
                         if (m0 < S::NN)
-                            store_out(reinterpret_cast<f32x4_t *>(Ae + m0), r);
+                            put(reinterpret_cast<f32x4_t *>(Ae + m0), r);
                     } else {
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
@@ -264,7 +271,7 @@ struct MfmaTile {
                     const int el = f / NV4, part = f - el * NV4;
                     const floatx4_t r =
                         *reinterpret_cast<const floatx4_t *>(so + el * L::OSTR + 4 * part);
-                    if (eg + el < E) store_out(reinterpret_cast<f32x4_t *>(dst + 4 * f), r);
+                    if (eg + el < E) put(reinterpret_cast<f32x4_t *>(dst + 4 * f), r);
                 }
                 wave_sync();
             }
