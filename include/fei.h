@@ -123,7 +123,8 @@ typedef struct fei_options {
                                contiguous run per chunk of elements (the
                                forward's default; the adjoint reads dA in R-row
                                chunks the same way).  R must divide n with
-                               R*n a multiple of 4; FEI_EUNSUPPORTED otherwise. */
+                               R*n a multiple of 4, and for the adjoint also
+                               R*n <= 48; FEI_EUNSUPPORTED otherwise. */
     int32_t reserved[4];    /* must be zero */
 } fei_options;
 

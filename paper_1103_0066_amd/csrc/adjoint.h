@@ -191,7 +191,11 @@ __device__ __forceinline__ void fold_piece(AccT *uacc, int flat0, const float (&
 #pragma unroll
             for (int nu = 0; nu < DIM; ++nu) {
                 const int g = sym_index(T::GD, mu * T::NC + cI, nu * T::NC + dJ);
-                uacc[g] += AccT(kval<FORM, DIM>(a, b, mu, nu)) * AccT(r[k]);
+                // Zero entries of K add no term (a select decided at compile
+                // time, not a branch, so the loops still unroll fully).
+                const float kv = kval<FORM, DIM>(a, b, mu, nu);
+                const AccT sum = uacc[g] + AccT(kv) * AccT(r[k]);
+                uacc[g] = (kv != 0.f) ? sum : uacc[g];
             }
     }
 }

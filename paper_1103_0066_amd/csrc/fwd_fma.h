@@ -30,10 +30,11 @@ namespace fei {
 
 // Block reference tensors, one per (form, dim), as compile-time constants
 // (the specializations holding the values are generated at build time).
-// Every index is known after unrolling, so the compiler folds K into the
-// code: zero entries drop out and +-1 entries become adds.  The result is
-// bit for bit that of the full multiply-add chain, since fma(0, x, a) = a and
-// fma(+-1, x, a) = a +- x exactly for finite x.
+// Every index is known after unrolling, so K is folded into the code: zero
+// entries are skipped by a compile-time test (the compiler may not drop
+// fma(0, x, a) by itself, since it is NaN for infinite x) and +-1 entries
+// become adds.  For finite inputs the result is bit for bit that of the full
+// multiply-add chain, since fma(0, x, a) = a and fma(+-1, x, a) = a +- x.
 template <int FORM, int DIM>
 struct KFold;
 
@@ -56,9 +57,13 @@ __device__ __forceinline__ float contract_entry(const float (&Gf)[Traits<FORM, D
 #pragma unroll
     for (int mu = 0; mu < DIM; ++mu)
 #pragma unroll
-        for (int nu = 0; nu < DIM; ++nu)
-            acc = fmaf(kval<FORM, DIM>(a, b, mu, nu),
-                       Gf[sym_index(T::GD, mu * T::NC + c, nu * T::NC + d)], acc);
+        for (int nu = 0; nu < DIM; ++nu) {
+            // A zero entry of K contributes no term.  The test is decided at
+            // compile time; without it the compiler must keep 0*G (IEEE: it
+            // is NaN for an infinite G) as a multiply-add.
+            const float k = kval<FORM, DIM>(a, b, mu, nu);
+            if (k != 0.f) acc = fmaf(k, Gf[sym_index(T::GD, mu * T::NC + c, nu * T::NC + d)], acc);
+        }
     return acc;
 }
 

@@ -11,6 +11,7 @@
 // column a - 1 of J-bar for a > 0, minus the sum of its columns for a = 0.
 #pragma once
 
+#include "geometry.h"
 #include "params.h"
 
 namespace fei {
@@ -186,11 +187,16 @@ __device__ __forceinline__ void gather_vertex(const GatherItem &it, int64_t v, i
 }
 
 // Thread t works on global vertex t / 8 (every lane of a group takes part in
-// the butterfly, including those past the last vertex).
+// the butterfly, including those past the last vertex).  For a single mesh,
+// whose vertices carry about equal work, each XCD takes one contiguous vertex
+// range, so the J-bar rows that neighbouring vertices share are re-read from
+// that XCD's L2; several meshes of unequal incidence counts keep the
+// round-robin order, which balances the XCDs' work.
 __global__ __launch_bounds__(256) void vertex_gather_kernel(const GatherItem *items, int n_items,
                                                             int64_t n_total)
 {
-    const int64_t t = blockIdx.x * 256ll + threadIdx.x;
+    const int64_t blk = n_items == 1 ? xcd_block(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
+    const int64_t t = blk * 256 + threadIdx.x;
     const int64_t gv = t / kGatherLanes;
     const int k = int(t % kGatherLanes);
     const bool live = gv < n_total;

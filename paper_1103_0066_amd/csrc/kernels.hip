@@ -116,10 +116,15 @@ FwdLauncher fwd_fma_if_ok()
     else return nullptr;
 }
 
+// The adjoint also holds two R-row chunks of dA per lane in registers (the
+// one being folded and the next one in flight): R*n <= 48 floats each.  The
+// larger chunks spill (3D elasticity with R = 6: 14x slower, measured), so
+// they are not offered.
 template <int F, int D, typename CT, int R>
 AdjLauncher adj_fma_if_ok()
 {
-    if constexpr (rows_ok<F, D, R>()) return &launch_adj_fma<F, D, CT, R>;
+    if constexpr (rows_ok<F, D, R>() && R * Traits<F, D>::N <= 48)
+        return &launch_adj_fma<F, D, CT, R>;
     else return nullptr;
 }
 

@@ -87,7 +87,7 @@ def test_adjoint_matches_oracle(case):
     _check_against_oracle(mesh, form, mu, lam, dA)
 
 
-@pytest.mark.parametrize("case,rows", [("elast3d", r) for r in (-1, 2, 3, 4, 6)] +
+@pytest.mark.parametrize("case,rows", [("elast3d", r) for r in (-1, 2, 3, 4)] +
                          [("lap3d", r) for r in (-1, 2, 4)] + [("p2_3d", r) for r in (-1, 2)] +
                          [("elast2d", r) for r in (-1, 2, 6)])
 def test_adjoint_staging_modes(case, rows):
@@ -113,6 +113,17 @@ def test_adjoint_staging_modes(case, rows):
         # separate kernel instantiations, whose multiply-add fusion may differ)
         if dmu is not None:
             assert _coeff_errors(mesh.coords, mesh.conn, dA, dmu, dlam, gm, gl).max() <= TOL_COEFF
+
+
+def test_adjoint_staging_beyond_register_budget_is_rejected():
+    # two 6-row chunks of a 12x12 dA (72 floats each) do not fit a lane's registers
+    mesh, form, mu, lam = _case("elast3d")
+    coords, conn = mesh_to_device(mesh)
+    dA = meshgen.upstream(mesh.n_elements, 12, 53)
+    with pytest.raises(fei.FeiError) as ex:
+        fei.integrate_adjoint(coords, conn, form, vec_to_device(dA), vec_to_device(mu),
+                              vec_to_device(lam), store_rows=6)
+    assert ex.value.status == fei._lib.FEI_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("rows", [0, -1, 2])
