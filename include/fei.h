@@ -186,7 +186,7 @@ int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream);
 /* ---- heterogeneous batches ------------------------------------------------
  * Many meshes and forms integrated by one launch of a HIP graph (the paper's
  * element batches, Sec. 4, applied across meshes).  Items are ordered
- * heaviest first (algorithmic bytes) and cut into 256-element tiles.  Two
+ * heaviest first (algorithmic bytes) and cut into 256-element tiles.  Four
  * graph shapes exist (fei_batch_config.mode):
  *   0  one persistent kernel for all forms: workgroups take tiles from a
  *      work counter (reset by a kernel node) until none are left;
@@ -194,7 +194,9 @@ int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream);
  *      branches of the graph (each kernel has the registers and LDS of its
  *      own form only);
  *   2  the single-mesh kernels of fei_integrate / fei_integrate_adjoint, one
- *      launch per item, the items of a group in turn on the group's branch.
+ *      launch per item, the items of a group in turn on the group's branch;
+ *   3  the kernels of mode 1, the groups one after another on one stream
+ *      (each has the whole GPU while it runs).
  * fei_batch_tune times candidate configurations on the caller's data and
  * rebuilds the graph with the fastest.
  * The plan owns its descriptor tables, work counter, streams and graphs, and
@@ -214,9 +216,10 @@ typedef struct fei_batch_item {
 } fei_batch_item;
 
 typedef struct fei_batch_config {
-    int32_t mode;           /* 0: persistent multi-form kernel, 1: per-group kernels,
-                               2: single-mesh kernels per item */
-    int32_t variant;        /* modes 0, 1: output staging, 0 wide, 1 narrow */
+    int32_t mode;           /* 0: persistent multi-form kernel, 1: per-group kernels
+                               on concurrent branches, 2: single-mesh kernels per
+                               item, 3: per-group kernels in sequence */
+    int32_t variant;        /* modes 0, 1, 3: output staging, 0 wide, 1 narrow */
     int32_t workgroups;     /* mode 0: persistent workgroups launched */
     int32_t tiles_per_pop;  /* mode 0: tiles taken from the counter per atomic */
     float ms;               /* measured time of this configuration (0: not tuned) */

@@ -138,11 +138,9 @@ hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t
         if ((e = launch_batch_reset(L.counter, s)) != hipSuccess) return e;
         if ((e = launch_batch(adj != 0, prec, c.variant, L, c.workgroups, s)) != hipSuccess) return e;
     } else {
-        if ((e = hipEventRecord(b->fork, s)) != hipSuccess) return e;
-        for (size_t g = 0; g < sd.groups.size(); ++g) {
-            const Group &G = sd.groups[g];
-            hipStream_t bs = b->branch[g];
-            if ((e = hipStreamWaitEvent(bs, b->fork, 0)) != hipSuccess) return e;
+        // one group's kernels on stream gs
+        auto run_group = [&](const Group &G, hipStream_t gs) -> hipError_t {
+            hipError_t r = hipSuccess;
             if (c.mode == 2 || (adj && G.n == 1)) {
                 // the single-mesh kernels, one launch per item of the group in
                 // turn (a group of one mesh always runs the adjoint this way:
@@ -153,21 +151,32 @@ hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t
                     if (adj) {
                         const AdjLauncher run = find_adjoint(v);
                         if (!run) return hipErrorInvalidValue;
-                        if ((e = run(d.ap, bs)) != hipSuccess) return e;
+                        if ((r = run(d.ap, gs)) != hipSuccess) return r;
                     } else {
                         const FwdLauncher run = find_forward(v);
                         if (!run) return hipErrorInvalidValue;
-                        if ((e = run(d.fp, bs)) != hipSuccess) return e;
+                        if ((r = run(d.fp, gs)) != hipSuccess) return r;
                     }
                 }
-            } else {
-                BatchLaunch L{grouped + G.off, G.n, 1, G.tiles, nullptr};
-                if ((e = launch_batch_group(adj != 0, gather, G.form, G.dim, prec, c.variant, L,
-                                            bs)) != hipSuccess)
-                    return e;
+                return r;
             }
-            if ((e = hipEventRecord(b->join[g], bs)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(s, b->join[g], 0)) != hipSuccess) return e;
+            BatchLaunch L{grouped + G.off, G.n, 1, G.tiles, nullptr};
+            return launch_batch_group(adj != 0, gather, G.form, G.dim, prec, c.variant, L, gs);
+        };
+        if (c.mode == 3) {
+            // the groups one after another on the caller's stream: each kernel
+            // has the whole GPU while it runs
+            for (const Group &G : sd.groups)
+                if ((e = run_group(G, s)) != hipSuccess) return e;
+        } else {
+            if ((e = hipEventRecord(b->fork, s)) != hipSuccess) return e;
+            for (size_t g = 0; g < sd.groups.size(); ++g) {
+                hipStream_t bs = b->branch[g];
+                if ((e = hipStreamWaitEvent(bs, b->fork, 0)) != hipSuccess) return e;
+                if ((e = run_group(sd.groups[g], bs)) != hipSuccess) return e;
+                if ((e = hipEventRecord(b->join[g], bs)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(s, b->join[g], 0)) != hipSuccess) return e;
+            }
         }
     }
     if (gather) e = launch_vertex_gather(b->gather.d_items, b->gather.n_items, b->gather.n_total, s);
@@ -482,6 +491,9 @@ int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *ch
             c.tiles_per_pop = 1;
             c.gather = gather;
             cand.push_back(c);
+            fei_batch_config m3 = c;
+            m3.mode = 3;
+            cand.push_back(m3);
             if (var == 0) {
                 fei_batch_config m2 = c;
                 m2.mode = 2;
@@ -536,8 +548,8 @@ int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *ch
 int fei_batch_set_config(fei_batch *b, int adjoint, const fei_batch_config *cfg)
 {
     if (!b || !cfg || (adjoint != 0 && adjoint != 1)) return fail(FEI_EINVAL, "bad argument");
-    if ((cfg->mode < 0 || cfg->mode > 2) || (cfg->variant != 0 && cfg->variant != 1))
-        return fail(FEI_EINVAL, "mode must be 0, 1 or 2 and variant 0 or 1");
+    if ((cfg->mode < 0 || cfg->mode > 3) || (cfg->variant != 0 && cfg->variant != 1))
+        return fail(FEI_EINVAL, "mode must be 0 to 3 and variant 0 or 1");
     if (cfg->mode == 0 && (cfg->workgroups < 1 || cfg->tiles_per_pop < 1))
         return fail(FEI_EINVAL, "mode 0 needs workgroups >= 1 and tiles_per_pop >= 1");
     if (cfg->gather != 0 && cfg->gather != 1) return fail(FEI_EINVAL, "gather must be 0 or 1");
