@@ -123,8 +123,10 @@ typedef struct fei_options {
                                contiguous run per chunk of elements (the
                                forward's default; the adjoint reads dA in R-row
                                chunks the same way).  R must divide n with
-                               R*n a multiple of 4, and for the adjoint also
-                               R*n <= 48; FEI_EUNSUPPORTED otherwise. */
+                               R*n a multiple of 4 (the forward also takes
+                               R = n for any n: 3x3 matrices are staged
+                               packed), and for the adjoint also R*n <= 48;
+                               FEI_EUNSUPPORTED otherwise. */
     int32_t reserved[4];    /* must be zero */
 } fei_options;
 

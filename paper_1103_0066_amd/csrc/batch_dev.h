@@ -22,8 +22,7 @@ template <int F, int D, int VAR>
 constexpr int batch_rows()
 {
     constexpr int N = Traits<F, D>::N;
-    if constexpr (N == 3) return 0;
-    else if constexpr (VAR == 0) return N;
+    if constexpr (VAR == 0 || N == 3) return N;
     else return 2;
 }
 

@@ -129,7 +129,8 @@ struct Stage {
     static constexpr int STR = CH + 4;
     static constexpr int NV4 = CH / 4;        // 16-byte pieces per element chunk
     static constexpr int NCHUNK = (R > 0) ? N / R : 0;
-    static_assert(R == 0 || (N % R == 0 && CH % 4 == 0), "bad chunk");
+    // R == N with n*n not a multiple of 4 (3x3): whole matrices, staged packed
+    static_assert(R == 0 || R == N || (N % R == 0 && CH % 4 == 0), "bad chunk");
 };
 
 // Orders this wave's LDS accesses around a point (the LDS executes one
@@ -156,9 +157,14 @@ struct FwdFmaTile {
     // and 53 KB of LDS per workgroup instead of 152 and 106 KB: two or three
     // resident workgroups per CU; measured faster than 64 or 16 at a time).
     static constexpr bool WHOLE = (R == T::N);
+    // Whole matrices that are not a whole number of 16-byte pieces (the 3x3
+    // matrices of the 2D P1 Laplacian): the wave's 64 matrices are staged
+    // packed, exactly as they lie in A, and leave as one contiguous run.
+    static constexpr bool PACKED = WHOLE && (S::NN % 4 != 0);
     static constexpr int EC = WHOLE ? (T::N >= 10 ? 32 : 64) : 64;
     static constexpr int NCH = WHOLE ? 64 / EC : S::NCHUNK;
-    static constexpr int LDS_BYTES = (R > 0) ? 4 * EC * S::STR * 4 : 0;
+    static constexpr int LDS_BYTES =
+        PACKED ? 4 * 64 * S::NN * 4 : ((R > 0) ? 4 * EC * S::STR * 4 : 0);
     // Staged stores: non-temporal for the 576-byte elasticity matrices, plain
     // for the smaller ones (measured on MI355X: 177 vs 182 us for 3D
     // elasticity, 133 vs 125 us for the 3D P2 Laplacian).
@@ -232,6 +238,35 @@ struct FwdFmaTile {
         if constexpr (R == 0) {
             const int64_t e = e0 + (threadIdx.x & 63);
             if (e < E) contract_store<FORM, DIM>(Au, p.A + e * (int64_t)S::NN);
+        } else if constexpr (PACKED) {
+            // The wave's 64 matrices start at e0 * n * n floats, a multiple of
+            // 64 * 9 * 4 bytes from the 16-byte aligned A: piece f of the run
+            // is 16-byte aligned; pieces past the last element's end are
+            // dropped, the one that straddles it is stored float by float.
+            const int lane = threadIdx.x & 63, wave = wave_id();
+            float *st = reinterpret_cast<float *>(smem) + wave * 64 * S::NN;
+#pragma unroll
+            for (int k = 0; k < S::NN; ++k) st[lane * S::NN + k] = Au[sym_index(S::N, k / S::N, k % S::N)];
+            wave_sync();
+            const int64_t left = E - e0;
+            const int nvalid = left <= 0 ? 0 : (left >= 64 ? 64 * S::NN : int(left) * S::NN);
+            constexpr int PIECES = 64 * S::NN / 4;
+            float *dst = p.A + e0 * (int64_t)S::NN;
+#pragma unroll
+            for (int k = 0; k < (PIECES + 63) / 64; ++k) {
+                const int f = lane + 64 * k;
+                if (f < PIECES) {
+                    if (4 * f + 4 <= nvalid) {
+                        put(reinterpret_cast<f32x4_t *>(dst + 4 * f),
+                            *reinterpret_cast<const f32x4_t *>(st + 4 * f));
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (4 * f + i < nvalid) dst[4 * f + i] = st[4 * f + i];
+                    }
+                }
+            }
+            wave_sync();
         } else {
             const int lane = threadIdx.x & 63, wave = wave_id();
             float *st = reinterpret_cast<float *>(smem) + wave * EC * S::STR;

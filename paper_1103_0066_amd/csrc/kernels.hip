@@ -88,6 +88,14 @@ constexpr bool rows_ok()
     return R == 0 || (N % R == 0 && (R * N) % 4 == 0 && 4 * 64 * (R * N + 4) * 4 <= 160 * 1024);
 }
 
+// The forward also stages whole matrices of any size (packed when n*n is not
+// a multiple of 4).
+template <int F, int D, int R>
+constexpr bool fwd_rows_ok()
+{
+    return rows_ok<F, D, R>() || R == Traits<F, D>::N;
+}
+
 // Tuned defaults of the staging rows (measured on MI355X).  Forward: whole
 // matrices (each staged chunk leaves as one contiguous run; row chunks leave
 // strided runs and measured up to 2.5x slower); adjoint: a third of the
@@ -95,8 +103,7 @@ constexpr bool rows_ok()
 template <int F, int D>
 constexpr int default_rows()
 {
-    constexpr int N = Traits<F, D>::N;
-    return (N * N) % 4 == 0 ? N : 0;
+    return Traits<F, D>::N;
 }
 
 template <int F, int D>
@@ -112,7 +119,7 @@ constexpr int default_adj_rows()
 template <int F, int D, typename CT, int R>
 FwdLauncher fwd_fma_if_ok()
 {
-    if constexpr (rows_ok<F, D, R>()) return &launch_fwd_fma<F, D, CT, R>;
+    if constexpr (fwd_rows_ok<F, D, R>()) return &launch_fwd_fma<F, D, CT, R>;
     else return nullptr;
 }
 

@@ -77,7 +77,7 @@ STAGING = [("elast3d", "fp32", r) for r in (-1, 2, 3, 4, 6, 12)] + \
           [("p2_3d", "fp32", r) for r in (-1, 2, 10)] + \
           [("elast2d", "fp32", r) for r in (-1, 2, 6)] + \
           [("p2_2d", "fp32", r) for r in (-1, 2, 6)] + \
-          [("lap2d_f64", "fp32", -1)] + \
+          [("lap2d_f64", "fp32", r) for r in (-1, 3)] + [("lap2d_f32", "fp32", -1)] + \
           [(c, pr, r) for c, n in (("elast3d", 12), ("lap3d", 4), ("p2_3d", 10), ("elast2d", 6))
            for pr in ("fp16x2", "bf16x3") for r in (-1, n)]
 
@@ -105,6 +105,22 @@ def test_every_tile_count_is_covered(precision, rows):
         A = _run(sub, "elastic_p1", mu[:E], lam[:E], precision, store_rows=rows)
         Ao = oracle.integrate("elastic_p1", m.coords, sub.conn, mu[:E], lam[:E])
         assert element_errors(A, Ao).max() <= TOL[precision], E
+
+
+@pytest.mark.parametrize("coord_dtype", [np.float32, np.float64])
+def test_packed_3x3_staging_stays_inside_its_elements(coord_dtype):
+    """The 3x3 matrices leave as one packed run per wave: every element is
+    written, and nothing past the last one (a sentinel tail stays NaN)."""
+    m = meshgen.square_mesh(40, 0.2, 24, coord_dtype)
+    coords, conn = mesh_to_device(m)
+    for E in (1, 2, 63, 64, 65, 127, 255, 256, 257, 3 * 256 + 130, m.n_elements):
+        buf = torch.full((E + 70, 3, 3), float("nan"), device=coords.device)
+        fei.integrate(coords, conn[:E].contiguous(), "laplace_p1", out=buf[:E])
+        torch.cuda.synchronize()
+        host = buf.cpu().numpy()
+        Ao = oracle.integrate("laplace_p1", m.coords, m.conn[:E])
+        assert element_errors(host[:E], Ao).max() <= TOL["fp32"], E
+        assert np.isnan(host[E:]).all(), E
 
 
 def test_unsupported_staging_is_rejected():
