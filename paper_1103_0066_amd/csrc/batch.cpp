@@ -45,6 +45,8 @@ struct Gather {
     bool ready = false;
     std::vector<void *> bufs;           // device allocations owned by the plan
     GatherItem *d_items = nullptr;
+    int32_t *d_xoff = nullptr;          // [8][n_items + 1] workgroups of each XCD per item
+    int64_t blocks_per_xcd = 0;
     int n_items = 0;
     int64_t n_total = 0;                // vertices over all items
 };
@@ -179,7 +181,9 @@ hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t
             }
         }
     }
-    if (gather) e = launch_vertex_gather(b->gather.d_items, b->gather.n_items, b->gather.n_total, s);
+    if (gather)
+        e = launch_vertex_gather(b->gather.d_items, b->gather.n_items, b->gather.d_xoff,
+                                 b->gather.blocks_per_xcd, s);
     return e;
 }
 
@@ -260,10 +264,28 @@ int ensure_gather(fei_batch *b)
         return rc;
     G.n_items = int(items.size());
     if (!items.empty()) {
-        if ((rc = alloc(items.size() * sizeof(GatherItem), reinterpret_cast<void **>(&G.d_items))))
+        // per XCD, the prefix sums of its share of each item's workgroups
+        const size_t ni = items.size();
+        std::vector<int32_t> xoff(8 * (ni + 1));
+        int64_t most = 0;
+        for (int x = 0; x < 8; ++x) {
+            int64_t acc = 0;
+            for (size_t j = 0; j < ni; ++j) {
+                xoff[x * (ni + 1) + j] = int32_t(acc);
+                acc += gather_slice_begin(items[j].n_vertices, x + 1) -
+                       gather_slice_begin(items[j].n_vertices, x);
+                if (acc > INT32_MAX) return fail(FEI_EUNSUPPORTED, "vertex gather: too many vertices");
+            }
+            xoff[x * (ni + 1) + ni] = int32_t(acc);
+            most = acc > most ? acc : most;
+        }
+        G.blocks_per_xcd = most;
+        if ((rc = alloc(ni * sizeof(GatherItem), reinterpret_cast<void **>(&G.d_items))) ||
+            (rc = alloc(xoff.size() * 4, reinterpret_cast<void **>(&G.d_xoff))))
             return rc;
-        e = hipMemcpy(G.d_items, items.data(), items.size() * sizeof(GatherItem),
-                      hipMemcpyHostToDevice);
+        e = hipMemcpy(G.d_items, items.data(), ni * sizeof(GatherItem), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(G.d_xoff, xoff.data(), xoff.size() * 4, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "gather table upload");
     }
     G.ready = true;

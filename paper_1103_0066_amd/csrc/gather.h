@@ -142,11 +142,11 @@ __global__ __launch_bounds__(256) void incidence_sort_kernel(Incidence g)
 typedef __attribute__((address_space(1))) const int32_t g_i32;
 typedef __attribute__((address_space(1))) const float g_f32;
 
-// Eight lanes per vertex: lane k of the vertex's group sums incidences
-// k, k + 8, k + 16, ... of its (sorted) list, then the eight partial sums are
-// combined by a fixed butterfly; the order of every addition is fixed by the
-// incidence list alone, so the result does not depend on the launch.
-constexpr int kGatherLanes = 8;
+// Eight lanes per vertex (kGatherLanes): lane k of the vertex's group sums
+// incidences k, k + 8, k + 16, ... of its (sorted) list, then the eight
+// partial sums are combined by a fixed butterfly; the order of every addition
+// is fixed by the incidence list alone, so the result does not depend on the
+// launch.
 
 template <int DIM>
 __device__ __forceinline__ void gather_vertex(const GatherItem &it, int64_t v, int k, bool live)
@@ -209,29 +209,33 @@ __device__ __forceinline__ void gather_vertex(const GatherItem &it, int64_t v, i
     }
 }
 
-// Thread t works on global vertex t / 8 (every lane of a group takes part in
-// the butterfly, including those past the last vertex).  For a single mesh,
-// whose vertices carry about equal work, each XCD takes one contiguous vertex
-// range, so the J-bar rows that neighbouring vertices share are re-read from
-// that XCD's L2; several meshes of unequal incidence counts keep the
-// round-robin order, which balances the XCDs' work.
+// Each vertex is summed by kGatherLanes consecutive threads, so a 256-thread
+// workgroup takes kGatherVerts consecutive vertices of one item.  Workgroups
+// are dispatched round-robin over the 8 XCDs; the workgroups of XCD x
+// (blockIdx % 8 == x) take, item after item, the x-th eighth of each item's
+// vertex blocks: every XCD gets the same share of every mesh (balanced work)
+// and a contiguous vertex range of it, so the J-bar rows that neighbouring
+// vertices share are re-read from that XCD's L2.  xoff[x][j] (host-built) is
+// the number of XCD x's workgroups before item j; workgroups past
+// xoff[x][n_items] have nothing to do.
 __global__ __launch_bounds__(256) void vertex_gather_kernel(const GatherItem *items, int n_items,
-                                                            int64_t n_total)
+                                                            const int32_t *xoff)
 {
-    const int64_t blk = n_items == 1 ? xcd_block(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
-    const int64_t t = blk * 256 + threadIdx.x;
-    const int64_t gv = t / kGatherLanes;
-    const int k = int(t % kGatherLanes);
-    const bool live = gv < n_total;
-    const int64_t gq = live ? gv : n_total - 1;
-    int lo = 0, hi = n_items - 1;
+    const int x = int(blockIdx.x % 8);
+    const int32_t i = int32_t(blockIdx.x / 8);
+    const int32_t *o = xoff + int64_t(x) * (n_items + 1);
+    if (i >= o[n_items]) return;                 // workgroup-uniform
+    int lo = 0, hi = n_items - 1;                // last item j with o[j] <= i
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].v_begin <= gq) lo = mid;
+        if (o[mid] <= i) lo = mid;
         else hi = mid - 1;
     }
     const GatherItem &it = items[lo];
-    const int64_t v = gq - it.v_begin;
+    const int64_t blk = gather_slice_begin(it.n_vertices, x) + (i - o[lo]);
+    const int64_t v = blk * kGatherVerts + threadIdx.x / kGatherLanes;
+    const int k = int(threadIdx.x % kGatherLanes);
+    const bool live = v < it.n_vertices;
     if (it.dim == 3) gather_vertex<3>(it, v, k, live);
     else gather_vertex<2>(it, v, k, live);
 }

@@ -389,13 +389,12 @@ hipError_t launch_incidence_build(const Incidence &g, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_vertex_gather(const GatherItem *items, int n_items, int64_t n_total,
-                                hipStream_t s)
+hipError_t launch_vertex_gather(const GatherItem *items, int n_items, const int32_t *xoff,
+                                int64_t blocks_per_xcd, hipStream_t s)
 {
-    if (n_total == 0) return hipSuccess;
-    const int64_t threads = n_total * kGatherLanes;
-    hipLaunchKernelGGL(vertex_gather_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s,
-                       items, n_items, n_total);
+    if (n_items == 0 || blocks_per_xcd == 0) return hipSuccess;
+    hipLaunchKernelGGL(vertex_gather_kernel, dim3(unsigned(8 * blocks_per_xcd)), dim3(256), 0, s,
+                       items, n_items, xoff);
     return hipGetLastError();
 }
 

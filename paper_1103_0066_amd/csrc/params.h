@@ -108,10 +108,24 @@ struct GatherItem {
     int32_t dim;
     int32_t atomic;            // 1 if another item accumulates into the same arrays
 };
+// Vertex gather geometry, shared by the kernel and the host that builds its
+// XCD table: kGatherLanes threads per vertex, kGatherVerts vertices per
+// 256-thread workgroup; XCD x takes the item's workgroup blocks from
+// gather_slice_begin(Nv, x) to gather_slice_begin(Nv, x + 1).
+constexpr int kGatherLanes = 8;
+constexpr int kGatherVerts = 256 / kGatherLanes;
+__host__ __device__ inline int64_t gather_slice_begin(int64_t n_vertices, int x)
+{
+    const int64_t nb = (n_vertices + kGatherVerts - 1) / kGatherVerts;
+    return x * nb / 8;
+}
+
 // Eight threads per vertex of every item: dx[v] += sum over the vertex's
 // incidences, combined in an order fixed by the sorted incidence list.
-hipError_t launch_vertex_gather(const GatherItem *items, int n_items, int64_t n_total,
-                                hipStream_t s);
+// xoff: int32[8][n_items + 1], per XCD the prefix sums of its workgroups per
+// item (gather_xcd_offsets); blocks_per_xcd: the largest of its last column.
+hipError_t launch_vertex_gather(const GatherItem *items, int n_items, const int32_t *xoff,
+                                int64_t blocks_per_xcd, hipStream_t s);
 
 hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad_dev,
                            hipStream_t s);
