@@ -562,14 +562,12 @@ struct AdjTile {
 // after the reverse pass, before this tile's atomics.  Vector-memory
 // operations complete in issue order, so every prefetch is issued before the
 // stores and atomics of the step it overlaps.
-// Without the vertex table the gather form fits two workgroups per CU in LDS;
-// asking for two waves per SIMD keeps it within 256 registers (measured 4%
-// faster despite a 12-byte spill).
-template <int FORM, int DIM, typename CT, int R, bool GATHER>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GATHER ? 2 : 1)))
-void adj_fma_kernel(AdjParams p, int64_t n_tiles)
+// Used for the scatter form, whose LDS vertex table leaves room for one
+// workgroup per CU: the pipelining hides that low occupancy.
+template <int FORM, int DIM, typename CT, int R>
+__global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p, int64_t n_tiles)
 {
-    using Tile = AdjTile<FORM, DIM, CT, R, GATHER>;
+    using Tile = AdjTile<FORM, DIM, CT, R, false>;
     using AccT = typename Tile::AccT;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
     const PersistentTiles pt(n_tiles);
@@ -609,6 +607,19 @@ void adj_fma_kernel(AdjParams p, int64_t n_tiles)
             t = tn;
         }
     }
+}
+
+// The gather form (no vertex table: 59 KB of LDS and under 200 registers for
+// 3D elasticity, two workgroups per CU): one workgroup per tile, tiles
+// remapped so that each XCD takes one contiguous range.  The hardware then
+// overlaps the workgroups' memory streams; measured faster than the pipelined
+// persistent loop for this form (3D elasticity plan: 255 vs 266 us).
+template <int FORM, int DIM, typename CT, int R, bool GATHER>
+__global__ __launch_bounds__(256) void adj_tile_kernel(AdjParams p)
+{
+    using Tile = AdjTile<FORM, DIM, CT, R, GATHER>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
+    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
 }
 
 }  // namespace fei

@@ -76,7 +76,15 @@ hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
 template <int F, int D, typename CT, int R, bool GATHER = false>
 hipError_t launch_adj_fma(const AdjParams &p, hipStream_t s)
 {
-    return launch_persistent<adj_fma_kernel<F, D, CT, R, GATHER>>(p, s);
+    if constexpr (GATHER) {
+        const int64_t n_tiles = (p.m.n_elements + kBlock - 1) / kBlock;
+        if (n_tiles == 0) return hipSuccess;
+        hipLaunchKernelGGL((adj_tile_kernel<F, D, CT, R, true>), dim3(unsigned(n_tiles)),
+                           dim3(kBlock), 0, s, p);
+        return hipGetLastError();
+    } else {
+        return launch_persistent<adj_fma_kernel<F, D, CT, R>>(p, s);
+    }
 }
 
 // Staging rows R that fit: R divides n, R*n floats is a whole number of
