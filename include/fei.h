@@ -56,7 +56,7 @@ enum fei_status {
     FEI_EINVAL = -1,      /* bad argument: null/misaligned pointer, bad form, dim, dtype, size */
     FEI_EDEVICE = -2,     /* a HIP call failed; message in fei_last_error() */
     FEI_ENOMEM = -3,      /* host or device allocation failed (plans only) */
-    FEI_EUNSUPPORTED = -4 /* valid request this build has no kernel for */
+    FEI_EUNSUPPORTED = -4 /* valid request the library has no kernel for */
 };
 
 enum fei_form {
