@@ -106,8 +106,10 @@ constexpr bool fwd_rows_ok()
 
 // Tuned defaults of the staging rows (measured on MI355X).  Forward: whole
 // matrices (each staged chunk leaves as one contiguous run; row chunks leave
-// strided runs and measured up to 2.5x slower); adjoint: a third of the
-// matrix or less, leaving LDS room for the vertex-merge table.
+// strided runs and measured up to 2.5x slower); adjoint: small chunks (two
+// rows of the 12 x 12 and 10 x 10 matrices), so that two workgroups with
+// their vertex-merge tables fit in a CU's LDS and registers (3D elasticity:
+// 250 us at R = 2 against 268-280 us at R = 3, 4).
 template <int F, int D>
 constexpr int default_rows()
 {
@@ -118,10 +120,17 @@ template <int F, int D>
 constexpr int default_adj_rows()
 {
     constexpr int N = Traits<F, D>::N;
-    if constexpr (N == 12) return 4;
-    else if constexpr (N == 4) return 4;
-    else if constexpr (N == 10 || N == 6) return 2;
+    if constexpr (N == 4) return 4;
+    else if constexpr (N == 12 || N == 10 || N == 6) return 2;
     else return 0;
+}
+
+// The gather form (no vertex table, one workgroup per tile) is fastest with
+// larger chunks for 3D elasticity (measured R = 4 against R = 2 and 3).
+template <int F, int D>
+constexpr int default_gather_rows()
+{
+    return Traits<F, D>::N == 12 ? 4 : default_adj_rows<F, D>();
 }
 
 template <int F, int D, typename CT, int R>
@@ -206,7 +215,7 @@ AdjLauncher adj_for_coords(const Variant &v)
     if (v.precision != P_FP32) return nullptr;
     if (v.gather) {   // plans' vertex gather: FP32 coordinates, default staging
         if (v.coord_f64 || v.rows != 0) return nullptr;
-        return &launch_adj_fma<F, D, float, default_adj_rows<F, D>(), true>;
+        return &launch_adj_fma<F, D, float, default_gather_rows<F, D>(), true>;
     }
     return v.coord_f64 ? adj_fma_rows<F, D, double>(v.rows) : adj_fma_rows<F, D, float>(v.rows);
 }
