@@ -107,9 +107,9 @@ constexpr bool fwd_rows_ok()
 // Tuned defaults of the staging rows (measured on MI355X).  Forward: whole
 // matrices (each staged chunk leaves as one contiguous run; row chunks leave
 // strided runs and measured up to 2.5x slower); adjoint: small chunks (two
-// rows of the 12 x 12 and 10 x 10 matrices), so that two workgroups with
-// their vertex-merge tables fit in a CU's LDS and registers (3D elasticity:
-// 250 us at R = 2 against 268-280 us at R = 3, 4).
+// rows of the 12 x 12 matrices), so that two workgroups with their
+// vertex-merge tables fit in a CU's LDS and registers (3D elasticity: 250 us
+// at R = 2 against 268-280 us at R = 3, 4).
 template <int F, int D>
 constexpr int default_rows()
 {
@@ -121,8 +121,8 @@ constexpr int default_adj_rows()
 {
     constexpr int N = Traits<F, D>::N;
     if constexpr (N == 4) return 4;
-    else if constexpr (N == 12 || N == 10 || N == 6) return 2;
-    else return 0;
+    else if constexpr (N == 12 || N == 6) return 2;
+    else return 0;     // 10 x 10: direct per-lane reads (197 vs 208 us at R = 2)
 }
 
 // The gather form (no vertex table, one workgroup per tile) is fastest with
@@ -130,7 +130,8 @@ constexpr int default_adj_rows()
 template <int F, int D>
 constexpr int default_gather_rows()
 {
-    return Traits<F, D>::N == 12 ? 4 : default_adj_rows<F, D>();
+    constexpr int N = Traits<F, D>::N;
+    return N == 12 ? 4 : (N == 10 ? 2 : default_adj_rows<F, D>());
 }
 
 template <int F, int D, typename CT, int R>
