@@ -146,7 +146,8 @@ hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t
             if (c.mode == 2 || (adj && G.n == 1)) {
                 // the single-mesh kernels, one launch per item of the group in
                 // turn (a group of one mesh always runs the adjoint this way:
-                // persistent, with cross-tile prefetch)
+                // the scatter form's persistent pipelined kernel, or the gather
+                // form's kernel without the group's item lookup)
                 for (int k = 0; k < G.n; ++k) {
                     const BatchItemDev &d = gather ? sd.grouped_g[G.off + k] : sd.grouped[G.off + k];
                     const Variant v{d.form, d.dim, 0, prec, 0, gather ? 1 : 0};
