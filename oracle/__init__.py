@@ -28,7 +28,10 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIB_PATH):
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+    # -std=c11 keeps floating-point contraction off (no FMA fusion), so the
+    # results do not depend on the instruction set; x86-64-v3 (AVX2, FMA) runs
+    # on every host this library is copied to, where -march=native might not.
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-std=c11", "-fopenmp", "-fPIC", "-shared",
            os.path.join(_HERE, "oracle.c"), "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
     os.replace(tmp, _LIB_PATH)
@@ -45,6 +48,8 @@ def _load():
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int32)
     lib.oracle_version.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = ctypes.c_int
     lib.oracle_gm_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
     lib.oracle_gm_rule.restype = ctypes.c_int
     lib.oracle_element.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
@@ -61,6 +66,11 @@ def _load():
     lib.oracle_gradient.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def set_threads(n: int) -> int:
+    """Number of OpenMP threads for the loops over elements (timing only)."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def _parse(form: str):
@@ -156,6 +166,35 @@ def gradient(form: str, coords, conn, dA, mu=None, lam=None, qs: int = 1):
     if rc:
         raise ValueError(f"oracle_gradient failed ({rc})")
     return gv, gm, gl, Lv
+
+
+def assemble(form: str, coords, conn, mu=None, lam=None, qs: int = 1):
+    """Global matrix K = sum_e P_e^T A_e P_e of a P1 form (the global portion of
+    the computation that element integration feeds, Sec. 1), as a
+    scipy.sparse CSR matrix over scalar DOFs with sorted column indices.
+
+    DOFs: vertex v for the Laplacian; dim * v + c for elasticity (node-major,
+    the element's DOF I = dim * a + c maps to dim * conn[e][a] + c).  Every
+    (row, column) pair that shares an element is stored, even where the sum is
+    zero.  The element matrices come from integrate(); COO entries with equal
+    (row, column) are summed by scipy's COO -> CSR conversion."""
+    import scipy.sparse as sp
+    kind, deg = _parse(form)
+    if deg != 1:
+        raise ValueError("assemble: P1 forms only")
+    conn = np.ascontiguousarray(conn, dtype=np.int64)
+    dim = np.asarray(coords).shape[1]
+    A = integrate(form, coords, conn, mu, lam, qs)
+    nc = dim if kind == 1 else 1
+    nv = np.asarray(coords).shape[0]
+    dofs = (nc * conn[:, :, None] + np.arange(nc)[None, None, :]).reshape(conn.shape[0], -1)
+    n = dofs.shape[1]
+    rows = np.broadcast_to(dofs[:, :, None], (conn.shape[0], n, n)).ravel()
+    cols = np.broadcast_to(dofs[:, None, :], (conn.shape[0], n, n)).ravel()
+    K = sp.coo_matrix((A.ravel(), (rows, cols)), shape=(nc * nv, nc * nv)).tocsr()
+    K.sum_duplicates()
+    K.sort_indices()
+    return K
 
 
 def vertex_gradient(gvert: np.ndarray, conn, n_vertices: int) -> np.ndarray:

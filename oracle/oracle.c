@@ -27,6 +27,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -37,6 +38,14 @@
 #define ORACLE_MAX_QP 128
 
 int oracle_version(void) { return 1; }
+
+/* Threads of the OpenMP loops over elements (n >= 1); returns the count the
+ * next parallel region will use.  Timing only: results do not depend on it. */
+int oracle_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
 
 static long factorial(int k)
 {

@@ -95,7 +95,14 @@ def test_reference_elasticity_closed_form(dim):
 
 
 def _p2_exact_reference(dim):
-    """P2 Laplacian on the unit simplex in exact rational arithmetic.
+    """P2 Laplacian on the unit simplex in exact rational arithmetic."""
+    K = _p2_exact_tensor(dim)
+    return sum(K[:, :, k, k] for k in range(dim))
+
+
+def _p2_exact_tensor(dim):
+    """K[i, j, mu, nu] = int_ref dphi_i/dxi_mu dphi_j/dxi_nu for the P2 basis on
+    the unit simplex, in exact rational arithmetic (returned as floats).
 
     grad phi_i = sum_a c_ia(lambda) grad lambda_a with c linear in lambda;
     int_ref lambda^alpha = alpha! / (|alpha| + d)!  (volume 1/d! included).
@@ -130,23 +137,73 @@ def _p2_exact_reference(dim):
         return tot
 
     n = len(c)
-    A = [[Fraction(0)] * n for _ in range(n)]
+    K = np.zeros((n, n, dim, dim))
     for i in range(n):
         for j in range(n):
-            s = Fraction(0)
-            for a in range(nv):
-                for b in range(nv):
-                    dot = sum(glam[a][k] * glam[b][k] for k in range(dim))
-                    if dot != 0 and c[i][a] and c[j][b]:
-                        s += dot * integ(c[i][a], c[j][b])
-            A[i][j] = s
-    return np.array([[float(v) for v in r] for r in A])
+            for mu in range(dim):
+                for nu in range(dim):
+                    s = Fraction(0)
+                    for a in range(nv):
+                        for b in range(nv):
+                            g = glam[a][mu] * glam[b][nu]
+                            if g != 0 and c[i][a] and c[j][b]:
+                                s += g * integ(c[i][a], c[j][b])
+                    K[i, j, mu, nu] = float(s)
+    return K
 
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_reference_p2_laplace_exact_rational(dim):
     A = oracle.element("laplace_p2", REF[dim])
     np.testing.assert_allclose(A, _p2_exact_reference(dim), atol=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_reference_p2_elasticity_exact_rational(dim):
+    """P2 elasticity on the unit simplex: int mu (delta_cd grad phi_i . grad phi_j
+    + d_d phi_i d_c phi_j) + lambda d_c phi_i d_d phi_j, node-major DOFs
+    I = dim * i + c, from the exact-rational P2 tensor (isotropic Lame form of
+    Sec. 3, eqs. 9-12, with the quadratic basis)."""
+    K = _p2_exact_tensor(dim)
+    nb = K.shape[0]
+    mu, lam = 1.7, 0.6
+    ref = np.zeros((dim * nb, dim * nb))
+    for i in range(nb):
+        for j in range(nb):
+            for c in range(dim):
+                for d in range(dim):
+                    v = mu * K[i, j, d, c] + lam * K[i, j, c, d]
+                    if c == d:
+                        v += mu * np.trace(K[i, j])
+                    ref[dim * i + c, dim * j + d] = v
+    A = oracle.element("elastic_p2", REF[dim], mu, lam)
+    np.testing.assert_allclose(A, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def _p2_nodes(x):
+    """P2 node positions: the vertices, then the edge midpoints in DOF order."""
+    nv = x.shape[0]
+    mids = [(x[a] + x[b]) / 2 for a in range(nv) for b in range(a + 1, nv)]
+    return np.vstack([x] + mids)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_p2_elasticity_rigid_modes_and_rank(dim):
+    """P2 elasticity on random simplices: symmetric, PSD, rigid motions sampled at
+    the P2 nodes span the null space exactly (rank n - 3 in 2D, n - 6 in 3D)."""
+    rng = np.random.default_rng(17)
+    for _ in range(15):
+        x = _random_simplex(rng, dim)
+        mu, lam = np.exp(rng.normal(size=2) * 0.5)
+        A = oracle.element("elastic_p2", x, mu, lam)
+        scale = np.abs(A).max()
+        np.testing.assert_allclose(A, A.T, rtol=0, atol=1e-13 * scale)
+        R = _rigid_modes(_p2_nodes(x), dim)
+        np.testing.assert_allclose(A @ R, 0, atol=1e-12 * scale)
+        ev = np.linalg.eigvalsh(A)
+        assert ev.min() > -1e-12 * scale
+        nrig = 3 if dim == 2 else 6
+        assert np.sum(ev > 1e-9 * scale) == A.shape[0] - nrig
 
 
 # --------------------------------------------------------------------------
@@ -230,10 +287,10 @@ def test_elasticity_is_symmetric_gradient_form(dim):
 # --------------------------------------------------------------------------
 
 def _rigid_modes(x, dim):
-    """Translations and infinitesimal rotations evaluated at P1 nodes, node-major."""
+    """Translations and infinitesimal rotations evaluated at the nodes x, node-major."""
     modes = []
     for c in range(dim):
-        t = np.zeros((dim + 1, dim)); t[:, c] = 1
+        t = np.zeros((x.shape[0], dim)); t[:, c] = 1
         modes.append(t.ravel())
     if dim == 2:
         modes.append(np.stack([-x[:, 1], x[:, 0]], axis=1).ravel())
@@ -364,6 +421,65 @@ def test_patch_elasticity_linear_field():
     vols = np.array([abs(np.linalg.det((X[c[1:]] - X[c[0]]).T)) / 6 for c in m.conn])
     ref = np.sum(vols * (2 * mu * np.sum(eps * eps) + lam * np.trace(eps) ** 2))
     assert np.isclose(u @ K @ u, ref, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Global assembly (sparse), pinned by dense loops, energy and kernel
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("form,dim", [("laplace_p1", 2), ("laplace_p1", 3), ("elastic_p1", 2),
+                                      ("elastic_p1", 3)])
+def test_assemble_equals_dense_loops(form, dim):
+    """The sparse COO -> CSR sum equals element-by-element dense accumulation
+    (a different route: index arithmetic written out per element)."""
+    m = (meshgen.square_mesh(4, 0.2, 31, np.float64) if dim == 2
+         else meshgen.cube_mesh(2, 2, 1, 0.15, 32, np.float64))
+    mu = lam = None
+    if form == "elastic_p1":
+        mu, lam = meshgen.lame(m.n_elements, 33)
+    K = oracle.assemble(form, m.coords, m.conn, mu, lam)
+    A = oracle.integrate(form, m.coords, m.conn, mu, lam)
+    nc = dim if form == "elastic_p1" else 1
+    D = _assemble(A, m.conn, nc, m.n_vertices)
+    np.testing.assert_allclose(K.toarray(), D, rtol=0, atol=1e-15 * np.abs(D).max())
+    # the pattern: exactly the DOF pairs that share an element
+    P = np.zeros((nc * m.n_vertices,) * 2, bool)
+    for c in m.conn:
+        d = np.array([nc * v + k for v in c for k in range(nc)])
+        P[np.ix_(d, d)] = True
+    S = np.zeros_like(P)
+    S[np.repeat(np.arange(K.shape[0]), np.diff(K.indptr)), K.indices] = True
+    assert np.array_equal(S, P)
+    assert np.all(np.diff(K.indices)[np.diff(np.repeat(np.arange(K.shape[0]),
+                                                       np.diff(K.indptr))) == 0] > 0)
+
+
+def test_assembled_laplace_energy_rowsums_symmetry():
+    """u = g.x linear: u^T K u = |g|^2 |Omega| (unit cube); constants in the kernel."""
+    m = meshgen.cube_mesh(3, 3, 3, 0.15, 34, np.float64)
+    K = oracle.assemble("laplace_p1", m.coords, m.conn)
+    g = np.array([-0.7, 0.2, 1.1])
+    u = m.coords @ g
+    assert np.isclose(u @ (K @ u), g @ g, rtol=1e-12)
+    assert np.abs(K @ np.ones(K.shape[0])).max() <= 1e-14 * abs(K).max()
+    assert abs(K - K.T).max() <= 1e-16 * abs(K).max()
+
+
+def test_assembled_elasticity_energy_and_rigid_modes():
+    """u = M x: u^T K u = sum_e vol_e (2 mu eps:eps + lam tr(eps)^2); the six rigid
+    motions of the whole body are in the kernel of K."""
+    m = meshgen.cube_mesh(3, 2, 2, 0.15, 35, np.float64)
+    mu, lam = meshgen.lame(m.n_elements, 36)
+    K = oracle.assemble("elastic_p1", m.coords, m.conn, mu, lam)
+    M = np.array([[0.2, -0.4, 0.1], [0.6, 0.3, -0.7], [0.15, 0.25, -0.9]])
+    u = (m.coords @ M.T).ravel()
+    eps = 0.5 * (M + M.T)
+    X = m.coords
+    vols = np.array([abs(np.linalg.det((X[c[1:]] - X[c[0]]).T)) / 6 for c in m.conn])
+    ref = np.sum(vols * (2 * mu * np.sum(eps * eps) + lam * np.trace(eps) ** 2))
+    assert np.isclose(u @ (K @ u), ref, rtol=1e-12)
+    R = _rigid_modes(m.coords, 3)
+    assert np.abs(K @ R).max() <= 1e-13 * abs(K).max()
 
 
 # --------------------------------------------------------------------------
