@@ -76,6 +76,19 @@ def _interior_mask(idx, n):
     return (idx > 0) & (idx < n)
 
 
+def _assert_positive(coords: np.ndarray, conn: np.ndarray):
+    """Input validity: every simplex is positively oriented (signed volume of its
+    edge vectors from vertex 0, in FP64 of the stored coordinates, is > 0)."""
+    X = coords.astype(np.float64)
+    e = [X[conn[:, k]] - X[conn[:, 0]] for k in range(1, conn.shape[1])]
+    if len(e) == 2:
+        vol = e[0][:, 0] * e[1][:, 1] - e[0][:, 1] * e[1][:, 0]
+    else:
+        vol = np.einsum("ij,ij->i", e[0], np.cross(e[1], e[2]))
+    if vol.size and not (vol > 0).all():
+        raise AssertionError(f"{int((vol <= 0).sum())} simplices are not positively oriented")
+
+
 def square_mesh(n: int, jitter: float = 0.2, seed: Optional[int] = None,
                 dtype=np.float64) -> Mesh:
     """Unit square, n x n cells of size h = 1/n, 2 n^2 triangles.
@@ -99,7 +112,9 @@ def square_mesh(n: int, jitter: float = 0.2, seed: Optional[int] = None,
     t0 = np.stack([v(0, 0), v(1, 0), v(1, 1)], axis=1)
     t1 = np.stack([v(0, 0), v(1, 1), v(0, 1)], axis=1)
     conn = np.stack([t0, t1], axis=1).reshape(-1, 3).astype(np.int32)
-    return Mesh(coords.astype(dtype), conn)
+    coords = coords.astype(dtype)
+    _assert_positive(coords, conn)
+    return Mesh(coords, conn)
 
 
 def cube_mesh(nx: int, ny: int, nz: int, jitter: float = 0.15,
@@ -147,7 +162,9 @@ def cube_mesh(nx: int, ny: int, nz: int, jitter: float = 0.15,
             vs = [vs[0], vs[1], vs[3], vs[2]]
         tets.append(np.stack(vs, axis=1))
     conn = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int32)
-    return Mesh(coords.astype(dtype), conn)
+    coords = coords.astype(dtype)
+    _assert_positive(coords, conn)
+    return Mesh(coords, conn)
 
 
 def flatten_elements(mesh: Mesh, count: int, seed: int, ratio: float = 1e-3) -> Mesh:
@@ -179,6 +196,7 @@ def flatten_elements(mesh: Mesh, count: int, seed: int, ratio: float = 1e-3) -> 
     coords = np.concatenate([mesh.coords, newv.astype(mesh.coords.dtype)], axis=0)
     conn = mesh.conn.copy()
     conn[sel, 3] = (mesh.n_vertices + np.arange(count)).astype(np.int32)
+    _assert_positive(coords, conn)
     return Mesh(coords, conn, flattened=sel)
 
 

@@ -90,8 +90,9 @@ __device__ __forceinline__ R adjugate(const R (&J)[2][2], R (&adj)[2][2])
 }
 
 // Quality test: kappa_F = |J|_F |adj J|_F / |det J| > tau, evaluated as
-// !(|J|^2 |adj|^2 <= tau^2 det^2) so that det == 0, NaN and tau2 < 0 all
-// select the FP64 path.
+// !(|J|^2 |adj|^2 <= tau^2 det^2) so that NaN and tau2 < 0 select the FP64
+// path.  det == 0 selects it explicitly: when adj J vanishes too (collinear
+// or coincident vertices) the product test reads 0 <= 0 and would pass.
 template <int DIM>
 __device__ __forceinline__ bool needs_fp64(const float (&J)[DIM][DIM],
                                            const float (&adj)[DIM][DIM], float det, float tau2)
@@ -104,7 +105,7 @@ __device__ __forceinline__ bool needs_fp64(const float (&J)[DIM][DIM],
             nj = fmaf(J[i][k], J[i][k], nj);
             na = fmaf(adj[i][k], adj[i][k], na);
         }
-    return !(nj * na <= tau2 * (det * det));
+    return !(nj * na <= tau2 * (det * det)) || det == 0.f;
 }
 
 // Folded geometric tensor: Gf[sym_index(p, q)], p <= q, scaled by

@@ -9,10 +9,15 @@ import torch
 TOL = {"fp32": 1e-5, "fp16x2": 1e-5, "bf16x2": 3e-5, "bf16x3": 1e-5}
 
 # Adjoint: vertex gradients are sums of ~24 partially cancelling FP32 terms
-# added by atomics, judged against the sum of the magnitudes of the terms;
+# added by atomics, judged against the sum of the magnitudes of the terms (the
+# FP32 bound of the forward applies: measured errors stay below 2e-6);
 # per-element coefficient gradients against the element's own scale.
-TOL_VERTEX = 1e-4
+TOL_VERTEX = 1e-5
 TOL_COEFF = 1e-5
+# Central differences of the oracle around a flattened tet (kappa ~ 3e3) carry
+# their own truncation and cancellation error; the GPU is held to this looser
+# bound only there, against the largest FD component.
+TOL_FD_FLAT = 1e-4
 
 
 def device():

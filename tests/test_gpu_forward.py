@@ -276,3 +276,95 @@ def test_full_laplace2d_every_element():
     A = fei.integrate(coords, conn, w.form, out=A).cpu().numpy()
     Ao = oracle.integrate(w.form, m.coords, m.conn)
     assert element_errors(A, Ao).max() <= TOL["fp32"]
+
+
+# ---------------------------------------------------------------------------
+# degenerate elements and non-finite coordinates
+# ---------------------------------------------------------------------------
+
+def _degenerate_mesh(dim):
+    """Regular elements around degenerate ones: collinear vertices (adj J = 0 in
+    3D) and all vertices at one point (J = 0).  Returns mesh, degenerate ids."""
+    if dim == 3:
+        X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1],
+                      [2, 0, 0], [3, 0, 0], [0.5, 0.5, 0.5]], np.float32)
+        conn = np.array([[0, 1, 2, 3],      # regular
+                         [0, 1, 4, 5],      # four collinear vertices
+                         [6, 6, 6, 6],      # one point
+                         [1, 2, 3, 6],      # regular
+                         [0, 4, 5, 3]],     # three collinear vertices + one: coplanar
+                        np.int32)
+        return meshgen.Mesh(X, conn), [1, 2, 4]
+    X = np.array([[0, 0], [1, 0], [0, 1], [2, 0], [0.3, 0.4]], np.float32)
+    conn = np.array([[0, 1, 2],             # regular
+                     [4, 4, 4],             # one point (J = 0, adj J = 0)
+                     [0, 1, 3],             # collinear
+                     [1, 2, 4]], np.int32)  # regular
+    return meshgen.Mesh(X, conn), [1, 2]
+
+
+@pytest.mark.parametrize("tau", [100.0, 0.0, math.inf])
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("form,dim", [("laplace_p1", 3), ("elastic_p1", 3), ("laplace_p1", 2),
+                                      ("elastic_p1", 2), ("laplace_p2", 3)])
+def test_degenerate_elements_are_counted_and_isolated(form, dim, precision, tau):
+    """det J == 0 -- also when adj J vanishes with it -- takes the FP64 path, is
+    counted as singular, and gives non-finite entries in that element only."""
+    mesh, bad = _degenerate_mesh(dim)
+    mu = lam = None
+    if form == "elastic_p1":
+        mu, lam = meshgen.lame(mesh.n_elements, 90)
+    cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+    A = _run(mesh, form, mu, lam, precision, tau=tau, counters=cnt)
+    good = np.setdiff1d(np.arange(mesh.n_elements), bad)
+    flagged = mesh.n_elements if tau <= 0 else len(bad)
+    assert cnt.cpu().tolist() == [flagged, len(bad)]
+    for e in bad:
+        assert not np.all(np.isfinite(A[e])), e
+    Ao = oracle.integrate(form, mesh.coords, mesh.conn[good],
+                          None if mu is None else mu[good], None if lam is None else lam[good])
+    assert np.all(np.isfinite(A[good]))
+    assert element_errors(A[good], Ao).max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("value", [float("nan"), float("inf"), -float("inf")])
+@pytest.mark.parametrize("precision", ["fp32", "fp16x2"])
+@pytest.mark.parametrize("case", ["lap3d", "elast3d", "lap2d_f64"])
+def test_nonfinite_coordinate_stays_in_its_elements(case, precision, value):
+    """A NaN or infinite coordinate reaches only the elements that use the vertex;
+    every other element is finite and matches the oracle (no lane or wave of the
+    kernels mixes elements)."""
+    mesh, form, mu, lam = _case(case)
+    X = mesh.coords.copy()
+    v = int(mesh.conn[len(mesh.conn) // 2, 2])
+    X[v, 1] = value
+    bad_mesh = meshgen.Mesh(X, mesh.conn)
+    A = _run(bad_mesh, form, mu, lam, precision)
+    touched = np.isin(mesh.conn, [v]).any(axis=1)
+    good = np.nonzero(~touched)[0]
+    assert np.all(np.isfinite(A[good]))
+    Ao = oracle.integrate(form, mesh.coords, mesh.conn[good],
+                          None if mu is None else mu[good], None if lam is None else lam[good])
+    assert element_errors(A[good], Ao).max() <= TOL[precision]
+    if value != value:    # NaN reaches every entry of the elements that use the vertex
+        assert np.isnan(A[touched]).all()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16x2"])
+def test_full_laplace_p2_3d_sampled(precision):
+    """3D P2 Laplacian (10 x 10) on the full 64^3 cube, as bench.py launches it."""
+    w = meshgen.lap3d(64)
+    m = w.mesh
+    coords, conn = mesh_to_device(m)
+    A = torch.full((m.n_elements, 10, 10), float("nan"), device=coords.device)
+    fei.integrate(coords, conn, "laplace_p2", precision=precision, out=A)
+    assert not bool(torch.isnan(A).any())
+    idx = _sample(m.n_elements, None, 20000, 9)
+    As = A[torch.from_numpy(idx).to(A.device)].cpu().numpy()
+    Ao = oracle.integrate("laplace_p2", m.coords, m.conn[idx])
+    err = element_errors(As, Ao)
+    print(f"  P2 sampled {len(idx)}: max err {err.max():.3e}")
+    assert err.max() <= TOL[precision]
+    # constants are in the kernel of every element matrix
+    rowsum = A.sum(dim=2).abs().amax(dim=1) / A.abs().amax(dim=(1, 2))
+    assert float(rowsum.max()) <= 20 * TOL[precision]
