@@ -181,6 +181,22 @@ int fei_integrate_adjoint(const fei_mesh *m, int form, const float *mu,
                           float *dz, float *dmu, float *dlam,
                           const fei_options *opt, void *stream);
 
+/* The adjoint of fei_integrate_adjoint with vertex gradients summed in an
+ * order fixed by the mesh, so every call gives the same bits (FP32
+ * coordinates only; store_rows must be 0).  Same arguments, same meaning:
+ * dx, dy, dz are accumulated (+=) -- without atomics, by one read-modify-write
+ * per vertex -- and dmu, dlam are overwritten.  Steps, all on `stream`: the
+ * vertex-to-element incidence of the mesh (CSR, built on the device), J-bar
+ * per element (the reverse of eqs. 5 and 8 per element), then each vertex
+ * sums the contributions of its elements in increasing element order.  The
+ * workspace, 4 (N_v + 1) + 4 N_v + 4 (dim + 1) E + 4 dim^2 E bytes (each part
+ * rounded up to 256), is taken with hipMallocAsync and released with
+ * hipFreeAsync on the stream.  FEI_ENOMEM if that allocation fails.        */
+int fei_integrate_adjoint_det(const fei_mesh *m, int form, const float *mu,
+                              const float *lam, const float *dA, float *dx, float *dy,
+                              float *dz, float *dmu, float *dlam,
+                              const fei_options *opt, void *stream);
+
 /* Checks conn against n_vertices on the device and returns the number of
  * out-of-range entries in *n_bad.  Synchronises the stream.                 */
 int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream);
@@ -262,7 +278,59 @@ int fei_batch_get_config(const fei_batch *b, int adjoint, fei_batch_config *out)
  * and tiles_per_pop >= 1; variant and gather are 0 or 1 (gather = 1 only for
  * the adjoint); reserved must be zero.                                      */
 int fei_batch_set_config(fei_batch *b, int adjoint, const fei_batch_config *cfg);
+/* Copies the vertex-to-element incidence the plan built for item `item` (an
+ * index into the list given to fei_batch_create) for the adjoint's vertex
+ * gather, so callers and tests can inspect it.  The incidence is CSR over
+ * vertices: ptr[v] .. ptr[v+1] index inc, whose entries are e * (dim + 1) + a
+ * (element e, local vertex a) in increasing order.
+ *   ptr  device int32[n_vertices + 1], written
+ *   inc  device int32[(dim + 1) * n_elements], written
+ * Asynchronous on `stream`.  FEI_EINVAL if the plan has not built its vertex
+ * gather (fei_batch_tune with adjoint = 1, or fei_batch_set_config with
+ * gather = 1) or the item is not part of the adjoint (no dA or no elements). */
+int fei_batch_copy_incidence(const fei_batch *b, int item, int32_t *ptr, int32_t *inc,
+                             void *stream);
 int fei_batch_destroy(fei_batch *b);
+
+/* ---- fused global assembly -------------------------------------------------
+ * The global matrix K = sum_e P_e^T A_e P_e of a P1 form (the global portion of
+ * the computation that element integration feeds, Sec. 1), with each A_e
+ * integrated on the fly (Sec. 3, eq. 1) and summed into K's values without
+ * ever being stored.  K is CSR over vertices with NC x NC blocks (NC = 1 for
+ * FEI_LAPLACE_P1, dim for FEI_ELASTIC_P1; block (i, j) entry (c, d) is the
+ * coefficient of DOF dim * j + d in row dim * i + c, the node-major DOF order
+ * of the element matrices).  Row i stores every vertex that shares an element
+ * with i, in increasing order, even where the sum is zero.
+ *
+ * A plan holds the pattern and the vertex-to-element incidence the kernel
+ * walks; it is built once per connectivity and serves any coordinates and
+ * coefficients on that connectivity. */
+typedef struct fei_assembly fei_assembly;
+
+/* Builds the plan of mesh m (its connectivity; coordinates are not read).
+ * Device-synchronizing: the connectivity is copied to the host, checked
+ * (FEI_EINVAL for an entry outside [0, n_vertices)) and the pattern built
+ * there.  FEI_EUNSUPPORTED for P2 forms and for a vertex with more than 256
+ * neighbours.  The plan owns its device arrays, released by
+ * fei_assembly_destroy.                                                     */
+int fei_assembly_create(const fei_mesh *m, int form, fei_assembly **out);
+/* Rows (= n_vertices), stored blocks, and the block side NC.                */
+int fei_assembly_info(const fei_assembly *a, int64_t *n_rows, int64_t *nnz, int32_t *block);
+/* Copies the pattern into device arrays rowptr [n_rows + 1] and colidx [nnz]
+ * (int32), asynchronously on `stream`.                                      */
+int fei_assembly_copy_pattern(const fei_assembly *a, int32_t *rowptr, int32_t *colidx,
+                              void *stream);
+/* values [nnz][NC][NC] FP32 (device, overwritten) = K of mesh m, which must
+ * have the dimension, vertex and element counts of the plan's mesh and the
+ * same connectivity (not re-checked: the kernel trusts the plan); FP32
+ * coordinates; mu, lam as for fei_integrate.  opt: precision must be FP32;
+ * tau and counters act as in fei_integrate (each element counted once).
+ * Every element is integrated once per vertex (by the wave that owns that
+ * vertex's row), so each block's sum is formed in LDS and written once.
+ * Asynchronous on `stream`.                                                 */
+int fei_assemble(const fei_assembly *a, const fei_mesh *m, const float *mu, const float *lam,
+                 float *values, const fei_options *opt, void *stream);
+int fei_assembly_destroy(fei_assembly *a);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import FORMS, PRECISIONS, FeiError
 
 __all__ = ["integrate", "integrate_adjoint", "element_matrices", "local_size",
-           "reference_tensor", "reference_scale", "validate_mesh", "Batch", "FeiError",
+           "reference_tensor", "reference_scale", "validate_mesh", "Batch", "Assembly", "FeiError",
            "FORMS", "PRECISIONS", "library_path"]
 
 
@@ -157,11 +157,13 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
                       tau: float = 100.0, dcoords: Optional[torch.Tensor] = None,
                       coeff_grads: bool = True, counters: Optional[torch.Tensor] = None,
                       dmu: Optional[torch.Tensor] = None, dlam: Optional[torch.Tensor] = None,
-                      store_rows: int = 0):
+                      store_rows: int = 0, deterministic: bool = False):
     """Gradients of L = sum_e <dA_e, A_e>.
 
     Returns (dcoords [dim, N_v] float32, accumulated into ``dcoords`` when given,
-    dmu [E] or None, dlam [E] or None; written into ``dmu``/``dlam`` when given)."""
+    dmu [E] or None, dlam [E] or None; written into ``dmu``/``dlam`` when given).
+    ``deterministic`` sums the vertex gradients in an order fixed by the mesh
+    (fei_integrate_adjoint_det: same bits on every call; FP32 coordinates)."""
     lib = _lib.load()
     m = _mesh(coords, conn)
     dev = coords.device
@@ -184,7 +186,8 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
     else:
         dmu = dlam = None
     o = _options("fp32", tau, counters, store_rows)
-    _lib.check(lib.fei_integrate_adjoint(
+    entry = lib.fei_integrate_adjoint_det if deterministic else lib.fei_integrate_adjoint
+    _lib.check(entry(
         ctypes.byref(m), _form_id(form), _ptr(mu), _ptr(lam), _ptr(dA),
         dcoords[0].data_ptr(), dcoords[1].data_ptr(),
         dcoords[2].data_ptr() if m.dim == 3 else None, _ptr(dmu), _ptr(dlam),
@@ -203,7 +206,15 @@ def validate_mesh(coords: torch.Tensor, conn: torch.Tensor) -> int:
 
 class _IntegrateFn(torch.autograd.Function):
     """Forward through fei_integrate; backward through fei_integrate_adjoint
-    (G is recomputed from the mesh, nothing but the inputs is saved)."""
+    (G is recomputed from the mesh, nothing but the inputs is saved).
+
+    The backward is the FP32 adjoint of the exact operator whatever precision
+    the forward used: for the split-precision forms it is the gradient of the
+    exact A, not of the rounded A that was returned (they differ by the
+    forward's stated error).  Vertex gradients are accumulated in FP32 and cast
+    to the dtype of ``coords`` (FP64 coordinates get FP32-accurate gradients).
+    Under ``torch.use_deterministic_algorithms(True)`` (FP32 coordinates) the
+    vertex gradients come from fei_integrate_adjoint_det, in a fixed order."""
 
     @staticmethod
     def forward(ctx, coords, mu, lam, conn, form, precision, tau):
@@ -216,8 +227,9 @@ class _IntegrateFn(torch.autograd.Function):
         coords, mu, lam, conn = ctx.saved_tensors
         dA = dA.contiguous()
         need_c = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        det = torch.are_deterministic_algorithms_enabled() and coords.dtype == torch.float32
         dc, dmu, dlam = integrate_adjoint(coords, conn, ctx.form, dA, mu, lam, tau=ctx.tau,
-                                          coeff_grads=need_c)
+                                          coeff_grads=need_c, deterministic=det)
         gc = dc.to(coords.dtype) if ctx.needs_input_grad[0] else None
         return (gc, dmu if ctx.needs_input_grad[1] else None,
                 dlam if ctx.needs_input_grad[2] else None, None, None, None, None)
@@ -226,8 +238,14 @@ class _IntegrateFn(torch.autograd.Function):
 def element_matrices(coords: torch.Tensor, conn: torch.Tensor, form: str,
                      mu: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
                      precision: str = "fp32", tau: float = 100.0) -> torch.Tensor:
-    """Autograd-aware element matrices: gradients flow to coords, mu and lam."""
+    """Autograd-aware element matrices: gradients flow to coords, mu and lam.
+
+    The backward is the FP32 adjoint of the exact operator for every
+    ``precision`` (for "fp16x2", "bf16x2", "bf16x3" the gradient of the exact A,
+    not of the split-precision A returned), accumulated in FP32 and cast to the
+    dtype of ``coords``; deterministic under torch.use_deterministic_algorithms."""
     return _IntegrateFn.apply(coords, mu, lam, conn, form, precision, tau)
 
 
 from .batch import Batch  # noqa: E402
+from .assembly import Assembly  # noqa: E402

@@ -24,9 +24,11 @@ ABI_VERSION = 2          # FEI_ABI_VERSION of the structs below
 
 EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_default",
            "fei_local_size", "fei_reference_tensor", "fei_reference_scale", "fei_integrate",
-           "fei_integrate_adjoint", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
+           "fei_integrate_adjoint", "fei_integrate_adjoint_det", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
            "fei_batch_run_adjoint", "fei_batch_tune", "fei_batch_get_config", "fei_batch_set_config",
-           "fei_batch_destroy")
+           "fei_batch_copy_incidence", "fei_batch_destroy", "fei_assembly_create",
+           "fei_assembly_info", "fei_assembly_copy_pattern", "fei_assemble",
+           "fei_assembly_destroy")
 
 
 class FeiMesh(ctypes.Structure):
@@ -100,6 +102,7 @@ def load():
     lib.fei_integrate_adjoint.argtypes = [ctypes.POINTER(FeiMesh), ctypes.c_int, f32p, f32p,
                                           f32p, f32p, f32p, f32p, f32p, f32p,
                                           ctypes.POINTER(FeiOptions), vp]
+    lib.fei_integrate_adjoint_det.argtypes = lib.fei_integrate_adjoint.argtypes
     lib.fei_validate_mesh.argtypes = [ctypes.POINTER(FeiMesh), ctypes.POINTER(i64), vp]
     lib.fei_batch_create.argtypes = [ctypes.POINTER(FeiBatchItem), ctypes.c_int,
                                      ctypes.POINTER(FeiOptions), ctypes.POINTER(vp)]
@@ -109,6 +112,14 @@ def load():
     lib.fei_batch_tune.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(FeiBatchConfig)]
     lib.fei_batch_get_config.argtypes = [vp, ctypes.c_int, ctypes.POINTER(FeiBatchConfig)]
     lib.fei_batch_set_config.argtypes = [vp, ctypes.c_int, ctypes.POINTER(FeiBatchConfig)]
+    lib.fei_batch_copy_incidence.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.fei_assembly_create.argtypes = [ctypes.POINTER(FeiMesh), ctypes.c_int, ctypes.POINTER(vp)]
+    lib.fei_assembly_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i32)]
+    lib.fei_assembly_copy_pattern.argtypes = [vp, vp, vp, vp]
+    lib.fei_assemble.argtypes = [vp, ctypes.POINTER(FeiMesh), f32p, f32p, f32p,
+                                 ctypes.POINTER(FeiOptions), vp]
+    lib.fei_assembly_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(lib, name)
     _lib = lib

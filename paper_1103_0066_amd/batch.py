@@ -86,6 +86,19 @@ class Batch:
         c.gather = int(cfg.get("gather", 0))
         _lib.check(_lib.load().fei_batch_set_config(self._h, int(adjoint), ctypes.byref(c)))
 
+    def incidence(self, item: int, stream: Optional[torch.cuda.Stream] = None):
+        """The vertex-to-element incidence the plan built for item ``item`` (CSR:
+        ``ptr`` [N_v + 1], ``inc`` [(dim + 1) E] with entries e * (dim + 1) + a),
+        copied into new device tensors.  Needs the vertex gather (an adjoint
+        tune, or ``set_config`` with ``gather=1``)."""
+        it = self.items[item]
+        coords, conn = it["coords"], it["conn"]
+        ptr = torch.empty(coords.shape[1] + 1, dtype=torch.int32, device=coords.device)
+        inc = torch.empty(conn.numel(), dtype=torch.int32, device=coords.device)
+        _lib.check(_lib.load().fei_batch_copy_incidence(self._h, int(item), ptr.data_ptr(),
+                                                        inc.data_ptr(), self._stream(stream)))
+        return ptr, inc
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.load().fei_batch_destroy(self._h)

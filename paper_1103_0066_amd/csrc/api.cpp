@@ -122,6 +122,108 @@ int check_coeffs(int form, const float *mu, const float *lam, int64_t E)
     return FEI_OK;
 }
 
+// Shared argument checks of the adjoint entry points.  Returns a negative
+// status, FEI_OK with p and v filled, or 1 when there is nothing to do (E = 0).
+int prepare_adjoint(const fei_mesh *m, int form, const float *mu, const float *lam,
+                    const float *dA, float *dx, float *dy, float *dz, float *dmu, float *dlam,
+                    const fei_options *opt, AdjParams &p, Variant &v)
+{
+    MeshView mv;
+    int rc = check_mesh(m, mv);
+    if (rc) return rc;
+    if (!valid_form(form)) return fail(FEI_EINVAL, "unknown form %d", form);
+    fei_options o = opt ? *opt : defaults();
+    if ((rc = check_options(o))) return rc;
+    if (o.precision != FEI_PREC_FP32)
+        return fail(FEI_EUNSUPPORTED, "the adjoint is FP32 only");
+    if ((rc = check_coeffs(form, mu, lam, m->n_elements))) return rc;
+    if (form != FEI_ELASTIC_P1 && (dmu || dlam))
+        return fail(FEI_EINVAL, "dmu/dlam must be NULL for a Laplacian form");
+    if (m->n_elements == 0) return 1;
+    if (!dA || !aligned(dA, 16)) return fail(FEI_EINVAL, "dA NULL or not 16-byte aligned");
+    if (!dx || !dy || (m->dim == 3 && !dz)) return fail(FEI_EINVAL, "dx/dy/dz missing");
+    if (!aligned(dx, 4) || !aligned(dy, 4) || (dz && !aligned(dz, 4)))
+        return fail(FEI_EINVAL, "dx/dy/dz misaligned");
+    v = Variant{form, m->dim, m->coord_dtype == FEI_F64, o.precision, o.store_rows, 0};
+    p.m = mv;
+    p.mu = mu;
+    p.lam = lam;
+    p.dA = dA;
+    p.dx = dx;
+    p.dy = dy;
+    p.dz = m->dim == 3 ? dz : nullptr;
+    p.dmu = dmu;
+    p.dlam = dlam;
+    p.counters = o.counters;
+    p.tau2 = tau2_of(o.tau);
+    p.jbar = nullptr;
+    return FEI_OK;
+}
+
+DetLayout det_layout(int dim, int64_t E, int64_t Nv)
+{
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    DetLayout L;
+    size_t o = 0;
+    L.ptr = o;
+    o += up(size_t(Nv + 1) * 4);
+    L.cursor = o;
+    o += up(size_t(Nv) * 4);
+    L.inc = o;
+    o += up(size_t(E) * size_t(dim + 1) * 4);
+    L.jbar = o;
+    o += up(size_t(E) * size_t(dim) * size_t(dim) * 4);
+    L.total = o;
+    return L;
+}
+
+int check_det(const fei_mesh *m, Variant &v)
+{
+    if (m->coord_dtype != FEI_F32)
+        return fail(FEI_EUNSUPPORTED, "the deterministic adjoint takes FP32 coordinates");
+    if (v.rows != 0)
+        return fail(FEI_EUNSUPPORTED, "the deterministic adjoint uses its own dA staging "
+                                      "(store_rows must be 0)");
+    if (m->n_elements * (m->dim + 1) > int64_t(INT32_MAX))
+        return fail(FEI_EUNSUPPORTED, "the deterministic adjoint needs (dim+1) * n_elements < 2^31");
+    v.gather = 1;
+    return find_adjoint(v) ? FEI_OK : fail(FEI_EUNSUPPORTED, "no adjoint kernel for this variant");
+}
+
+// Incidence build, J-bar adjoint and vertex gather on stream s, in the
+// workspace at base (layout L, 256-byte aligned parts).  Every part that must
+// start at zero is cleared by the incidence build's own kernels.
+int enqueue_adjoint_det(AdjParams p, const Variant &v, void *base, const DetLayout &L,
+                        hipStream_t s)
+{
+    char *b = static_cast<char *>(base);
+    int32_t *ptr = reinterpret_cast<int32_t *>(b + L.ptr);
+    int32_t *cursor = reinterpret_cast<int32_t *>(b + L.cursor);
+    int32_t *inc = reinterpret_cast<int32_t *>(b + L.inc);
+    float *jbar = reinterpret_cast<float *>(b + L.jbar);
+    const int nv = p.m.n_elements > 0 ? v.dim + 1 : 0;
+    Incidence g{p.m.conn, p.m.n_elements, p.m.n_vertices, nv, ptr, inc, cursor};
+    hipError_t e = launch_incidence_build(g, s);
+    if (e != hipSuccess) return hip_fail(e, "incidence build");
+    p.jbar = jbar;
+    const AdjLauncher launch = find_adjoint(v);
+    if (!launch) return fail(FEI_EUNSUPPORTED, "no adjoint kernel for this variant");
+    if ((e = launch(p, s)) != hipSuccess) return hip_fail(e, "adjoint launch");
+    GatherItem gi{};
+    gi.ptr = ptr;
+    gi.inc = inc;
+    gi.jbar = jbar;
+    gi.dx = p.dx;
+    gi.dy = p.dy;
+    gi.dz = p.dz;
+    gi.v_begin = 0;
+    gi.n_vertices = p.m.n_vertices;
+    gi.dim = v.dim;
+    gi.atomic = 0;
+    if ((e = launch_vertex_gather_one(gi, s)) != hipSuccess) return hip_fail(e, "vertex gather");
+    return FEI_OK;
+}
+
 }  // namespace host
 }  // namespace fei
 
@@ -256,40 +358,36 @@ int fei_integrate_adjoint(const fei_mesh *m, int form, const float *mu, const fl
                           const float *dA, float *dx, float *dy, float *dz, float *dmu,
                           float *dlam, const fei_options *opt, void *stream)
 {
-    MeshView mv;
-    int rc = check_mesh(m, mv);
-    if (rc) return rc;
-    if (!valid_form(form)) return fail(FEI_EINVAL, "unknown form %d", form);
-    fei_options o = opt ? *opt : defaults();
-    if ((rc = check_options(o))) return rc;
-    if (o.precision != FEI_PREC_FP32)
-        return fail(FEI_EUNSUPPORTED, "the adjoint is FP32 only");
-    if ((rc = check_coeffs(form, mu, lam, m->n_elements))) return rc;
-    if (form != FEI_ELASTIC_P1 && (dmu || dlam))
-        return fail(FEI_EINVAL, "dmu/dlam must be NULL for a Laplacian form");
-    if (m->n_elements == 0) return FEI_OK;
-    if (!dA || !aligned(dA, 16)) return fail(FEI_EINVAL, "dA NULL or not 16-byte aligned");
-    if (!dx || !dy || (m->dim == 3 && !dz)) return fail(FEI_EINVAL, "dx/dy/dz missing");
-    if (!aligned(dx, 4) || !aligned(dy, 4) || (dz && !aligned(dz, 4)))
-        return fail(FEI_EINVAL, "dx/dy/dz misaligned");
-    const Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision, o.store_rows};
+    AdjParams p;
+    Variant v;
+    int rc = prepare_adjoint(m, form, mu, lam, dA, dx, dy, dz, dmu, dlam, opt, p, v);
+    if (rc) return rc < 0 ? rc : FEI_OK;
     AdjLauncher launch = find_adjoint(v);
     if (!launch) return fail(FEI_EUNSUPPORTED, "no adjoint kernel for this variant");
-    AdjParams p;
-    p.m = mv;
-    p.mu = mu;
-    p.lam = lam;
-    p.dA = dA;
-    p.dx = dx;
-    p.dy = dy;
-    p.dz = m->dim == 3 ? dz : nullptr;
-    p.dmu = dmu;
-    p.dlam = dlam;
-    p.counters = o.counters;
-    p.tau2 = tau2_of(o.tau);
-    p.jbar = nullptr;
     hipError_t e = launch(p, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    return FEI_OK;
+}
+
+int fei_integrate_adjoint_det(const fei_mesh *m, int form, const float *mu, const float *lam,
+                              const float *dA, float *dx, float *dy, float *dz, float *dmu,
+                              float *dlam, const fei_options *opt, void *stream)
+{
+    AdjParams p;
+    Variant v;
+    int rc = prepare_adjoint(m, form, mu, lam, dA, dx, dy, dz, dmu, dlam, opt, p, v);
+    if (rc) return rc < 0 ? rc : FEI_OK;
+    if ((rc = check_det(m, v))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const DetLayout L = det_layout(m->dim, m->n_elements, m->n_vertices);
+    void *base = nullptr;
+    hipError_t e = hipMallocAsync(&base, L.total, s);
+    if (e != hipSuccess) return fail(FEI_ENOMEM, "deterministic adjoint workspace: %s",
+                                     hipGetErrorString(e));
+    rc = enqueue_adjoint_det(p, v, base, L, s);
+    e = hipFreeAsync(base, s);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return FEI_OK;
 }
 

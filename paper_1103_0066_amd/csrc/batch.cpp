@@ -49,6 +49,9 @@ struct Gather {
     int64_t blocks_per_xcd = 0;
     int n_items = 0;
     int64_t n_total = 0;                // vertices over all items
+    std::vector<int32_t> keys;          // caller's item index of each gather item
+    std::vector<GatherItem> host_items; // host copy of the gather descriptors
+    std::vector<int64_t> n_elements;    // elements of each gather item
 };
 
 double item_bytes(const fei_batch_item &it)
@@ -237,6 +240,8 @@ int ensure_gather(fei_batch *b)
         gi.dim = d.dim;
         gi.atomic = 0;
         items.push_back(gi);
+        G.keys.push_back(d.key);
+        G.n_elements.push_back(E);
         jbar_of.push_back({d.key, jbar});
         G.n_total += Nv;
     }
@@ -264,6 +269,7 @@ int ensure_gather(fei_batch *b)
     if ((rc = upload(with_jbar(sd.all), &sd.d_all_g)) || (rc = upload(sd.grouped_g, &sd.d_grouped_g)))
         return rc;
     G.n_items = int(items.size());
+    G.host_items = items;
     if (!items.empty()) {
         // per XCD, the prefix sums of its share of each item's workgroups
         const size_t ni = items.size();
@@ -585,6 +591,25 @@ int fei_batch_set_config(fei_batch *b, int adjoint, const fei_batch_config *cfg)
     }
     b->side[adjoint].cfg = *cfg;
     return build_graph(b, adjoint);
+}
+
+int fei_batch_copy_incidence(const fei_batch *b, int item, int32_t *ptr, int32_t *inc,
+                             void *stream)
+{
+    if (!b || !ptr || !inc) return fail(FEI_EINVAL, "bad argument");
+    const Gather &G = b->gather;
+    if (!G.ready) return fail(FEI_EINVAL, "the plan has not built its vertex gather");
+    for (size_t j = 0; j < G.keys.size(); ++j) {
+        if (G.keys[j] != item) continue;
+        const GatherItem &gi = G.host_items[j];
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t nptr = size_t(gi.n_vertices + 1) * 4;
+        const size_t ninc = size_t(G.n_elements[j]) * size_t(gi.dim + 1) * 4;
+        hipError_t e = hipMemcpyAsync(ptr, gi.ptr, nptr, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(inc, gi.inc, ninc, hipMemcpyDeviceToDevice, s);
+        return e == hipSuccess ? FEI_OK : hip_fail(e, "incidence copy");
+    }
+    return fail(FEI_EINVAL, "item %d has no vertex gather in this plan", item);
 }
 
 int fei_batch_destroy(fei_batch *b)

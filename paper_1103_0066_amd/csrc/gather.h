@@ -240,4 +240,19 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(const GatherItem *it
     else gather_vertex<2>(it, v, k, live);
 }
 
+// The same gather for one item passed by value (single calls, which keep no
+// device descriptor table): XCD x takes blocks gather_slice_begin(Nv, x) ..
+// gather_slice_begin(Nv, x + 1) of the item; the grid is 8 x the largest slice.
+__global__ __launch_bounds__(256) void vertex_gather_one_kernel(GatherItem it)
+{
+    const int x = int(blockIdx.x % 8);
+    const int64_t blk = gather_slice_begin(it.n_vertices, x) + int64_t(blockIdx.x / 8);
+    if (blk >= gather_slice_begin(it.n_vertices, x + 1)) return;   // workgroup-uniform
+    const int64_t v = blk * kGatherVerts + threadIdx.x / kGatherLanes;
+    const int k = int(threadIdx.x % kGatherLanes);
+    const bool live = v < it.n_vertices;
+    if (it.dim == 3) gather_vertex<3>(it, v, k, live);
+    else gather_vertex<2>(it, v, k, live);
+}
+
 }  // namespace fei

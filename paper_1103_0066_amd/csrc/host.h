@@ -26,6 +26,20 @@ int check_options(const fei_options &o);
 float tau2_of(float tau);
 int check_mesh(const fei_mesh *m, MeshView &mv);
 int check_coeffs(int form, const float *mu, const float *lam, int64_t E);
+int prepare_adjoint(const fei_mesh *m, int form, const float *mu, const float *lam,
+                    const float *dA, float *dx, float *dy, float *dz, float *dmu, float *dlam,
+                    const fei_options *opt, AdjParams &p, Variant &v);
+
+// Workspace of the deterministic adjoint: the vertex-to-element incidence
+// (ptr, cursor, inc) and J-bar per element, each part 256-byte aligned.
+struct DetLayout {
+    size_t ptr, cursor, inc, jbar, total;
+};
+DetLayout det_layout(int dim, int64_t E, int64_t Nv);
+// Checks a prepared adjoint for the deterministic path; sets v.gather.
+int check_det(const fei_mesh *m, Variant &v);
+int enqueue_adjoint_det(AdjParams p, const Variant &v, void *base, const DetLayout &L,
+                        hipStream_t s);
 
 }  // namespace host
 }  // namespace fei

@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "adjoint.h"
+#include "assemble.h"
 #include "batch_dev.h"
 #include "gather.h"
 #include "fwd_fma.h"
@@ -413,6 +414,36 @@ hipError_t launch_vertex_gather(const GatherItem *items, int n_items, const int3
     if (n_items == 0 || blocks_per_xcd == 0) return hipSuccess;
     hipLaunchKernelGGL(vertex_gather_kernel, dim3(unsigned(8 * blocks_per_xcd)), dim3(256), 0, s,
                        items, n_items, xoff);
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex_gather_one(const GatherItem &it, hipStream_t s)
+{
+    if (it.n_vertices <= 0) return hipSuccess;
+    int64_t most = 0;
+    for (int x = 0; x < 8; ++x) {
+        const int64_t n = gather_slice_begin(it.n_vertices, x + 1) - gather_slice_begin(it.n_vertices, x);
+        most = n > most ? n : most;
+    }
+    if (most == 0) return hipSuccess;
+    hipLaunchKernelGGL(vertex_gather_one_kernel, dim3(unsigned(8 * most)), dim3(256), 0, s, it);
+    return hipGetLastError();
+}
+
+int assemble_chunk_rows() { return kAsmRows; }
+int assemble_chunk_slots() { return kAsmSlots; }
+
+hipError_t launch_assemble(int form, int dim, const AsmParams &p, hipStream_t s)
+{
+    if (p.n_chunks <= 0) return hipSuccess;
+    const unsigned grid = unsigned((p.n_chunks + 3) / 4);
+    switch (form * 4 + dim) {
+    case LAP1 * 4 + 2: hipLaunchKernelGGL((assemble_kernel<LAP1, 2>), dim3(grid), dim3(256), 0, s, p); break;
+    case LAP1 * 4 + 3: hipLaunchKernelGGL((assemble_kernel<LAP1, 3>), dim3(grid), dim3(256), 0, s, p); break;
+    case ELA1 * 4 + 2: hipLaunchKernelGGL((assemble_kernel<ELA1, 2>), dim3(grid), dim3(256), 0, s, p); break;
+    case ELA1 * 4 + 3: hipLaunchKernelGGL((assemble_kernel<ELA1, 3>), dim3(grid), dim3(256), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

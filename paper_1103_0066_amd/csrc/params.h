@@ -126,8 +126,28 @@ __host__ __device__ inline int64_t gather_slice_begin(int64_t n_vertices, int x)
 // item (gather_xcd_offsets); blocks_per_xcd: the largest of its last column.
 hipError_t launch_vertex_gather(const GatherItem *items, int n_items, const int32_t *xoff,
                                 int64_t blocks_per_xcd, hipStream_t s);
+// The gather of one item (single calls): no device tables needed.
+hipError_t launch_vertex_gather_one(const GatherItem &it, hipStream_t s);
 
 hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad_dev,
                            hipStream_t s);
+
+// Fused global assembly (P1 forms): rows of the global matrix gathered by
+// waves, one host-built chunk of rows per wave.
+struct AsmParams {
+    MeshView m;
+    const float *mu, *lam;           // elasticity only
+    const int32_t *ptr, *inc;        // vertex-to-element incidence (CSR, sorted)
+    const int32_t *rowptr, *colidx;  // the pattern: CSR over vertices, sorted columns
+    const int32_t *chunks;           // [n_chunks + 1]: first row of each wave's chunk
+    int64_t n_chunks;
+    float *values;                   // [nnz][NC][NC]
+    int32_t *counters;
+    float tau2;
+};
+// Rows (kAsmRows) and blocks (kAsmSlots) one chunk may hold.
+int assemble_chunk_rows();
+int assemble_chunk_slots();
+hipError_t launch_assemble(int form, int dim, const AsmParams &p, hipStream_t s);
 
 }  // namespace fei

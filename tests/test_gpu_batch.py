@@ -282,3 +282,91 @@ def test_heterogeneous_workload_sampled():
                               None if w.lam is None else w.lam[idx])
         assert element_errors(A, Ao).max() <= TOL["fp32"], w.name
     b.close()
+
+
+def _workload_items(with_adjoint):
+    wl = meshgen.batch_items()
+    items = []
+    for k, w in enumerate(wl):
+        m = w.mesh
+        it = {"form": w.form, "coords": torch.from_numpy(m.soa()).to(DEV),
+              "conn": torch.from_numpy(m.conn).to(DEV)}
+        if w.mu is not None:
+            it["mu"], it["lam"] = torch.from_numpy(w.mu).to(DEV), torch.from_numpy(w.lam).to(DEV)
+        if with_adjoint:
+            dA = meshgen.upstream(m.n_elements, w.n_local, 2000 + k)
+            it["dA_host"] = dA
+            it["dA"] = torch.from_numpy(dA).to(DEV)
+            it["dcoords"] = torch.zeros((m.dim, m.n_vertices), dtype=torch.float32, device=DEV)
+            if w.mu is not None:
+                it["dmu"] = torch.full((m.n_elements,), float("nan"), device=DEV)
+                it["dlam"] = torch.full((m.n_elements,), float("nan"), device=DEV)
+        items.append(it)
+    return wl, items
+
+
+@pytest.mark.parametrize("how", ["tuned", "mode3_gather"])
+def test_heterogeneous_workload_adjoint_sampled(how):
+    """The 64-mesh adjoint (bench.py's batch adjoint leg: tuned, which picks the
+    vertex gather), sampled per mesh: vertices against the oracle over all their
+    incident elements, coefficient gradients per element; the incidence of the
+    largest mesh against a host CSR."""
+    wl, items = _workload_items(True)
+    b = fei.Batch(items)
+    if how == "tuned":
+        cfg = b.tune(adjoint=True)
+        print(f"[batch adjoint] tuned {cfg}", flush=True)
+    else:
+        b.set_config({"mode": 3, "variant": 1, "gather": 1}, adjoint=True)
+    for it in items:                 # the tuner's trials accumulated into dcoords
+        it["dcoords"].zero_()
+    torch.cuda.synchronize()
+    b.run_adjoint()
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(4))
+    worst = 0.0
+    for k, (w, it) in enumerate(zip(wl, items)):
+        m = w.mesh
+        g = it["dcoords"].cpu().numpy().T.astype(np.float64)
+        assert np.all(np.isfinite(g)), w.name
+        verts = np.union1d(rng.choice(m.n_vertices, min(40, m.n_vertices), replace=False),
+                           [m.n_vertices - 1])
+        inc = np.nonzero(np.isin(m.conn, verts).any(axis=1))[0]
+        dA = it["dA_host"]
+        gv, _, _, _ = oracle.gradient(w.form, m.coords, m.conn[inc], dA[inc],
+                                      None if w.mu is None else w.mu[inc],
+                                      None if w.lam is None else w.lam[inc])
+        go = oracle.vertex_gradient(gv, m.conn[inc], m.n_vertices)[verts]
+        sc = vertex_scale(gv, m.conn[inc], m.n_vertices)[verts]
+        ok = sc > 0
+        assert np.all(g[verts][~ok] == 0), w.name     # vertices no kept element uses
+        err = (np.abs(g[verts] - go).max(axis=1)[ok] / sc[ok]).max()
+        worst = max(worst, err)
+        assert err <= TOL_VERTEX, (w.name, err)
+        if w.mu is not None:
+            E = m.n_elements
+            idx = np.union1d(rng.choice(E, min(150, E), replace=False), [0, E - 1])
+            _, gm, gl, _ = oracle.gradient(w.form, m.coords, m.conn[idx], dA[idx], w.mu[idx],
+                                           w.lam[idx])
+            dmu = it["dmu"].cpu().numpy()[idx]
+            dlam = it["dlam"].cpu().numpy()[idx]
+            Am = oracle.integrate(w.form, m.coords, m.conn[idx], np.ones(len(idx)),
+                                  np.zeros(len(idx))).reshape(len(idx), -1)
+            Al = oracle.integrate(w.form, m.coords, m.conn[idx], np.zeros(len(idx)),
+                                  np.ones(len(idx))).reshape(len(idx), -1)
+            d2 = np.abs(dA[idx]).reshape(len(idx), -1)
+            assert (np.abs(dmu - gm) / (d2 * np.abs(Am)).sum(axis=1)).max() <= TOL_COEFF
+            assert (np.abs(dlam - gl) / (d2 * np.abs(Al)).sum(axis=1)).max() <= TOL_COEFF
+    print(f"  worst sampled vertex err over 64 meshes {worst:.3e}")
+    # the incidence of the largest mesh (> 16k vertices: the scan's 16-wide loops run)
+    big = int(np.argmax([w.mesh.n_vertices for w in wl]))
+    m = wl[big].mesh
+    assert m.n_vertices > 16384
+    ptr, inc = b.incidence(big)
+    deg = np.bincount(m.conn.ravel(), minlength=m.n_vertices)
+    assert np.array_equal(ptr.cpu().numpy(), np.concatenate([[0], np.cumsum(deg)]))
+    ih = inc.cpu().numpy()
+    owner = m.conn.ravel()[ih]
+    assert np.array_equal(owner, np.repeat(np.arange(m.n_vertices), deg))
+    assert np.all(np.diff(ih)[np.diff(owner) == 0] > 0)
+    b.close()
