@@ -64,6 +64,9 @@ def _load():
                                     ctypes.c_int64, dp, dp, dp, ctypes.c_int64,
                                     ip, dp, dp, dp, ctypes.c_int, dp, dp, dp, dp]
     lib.oracle_gradient.restype = ctypes.c_int
+    lib.oracle_integrate_w.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp, dp,
+                                       ctypes.c_int64, ip, dp, ctypes.c_int, dp]
+    lib.oracle_integrate_w.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -139,6 +142,29 @@ def integrate(form: str, coords, conn, mu=None, lam=None, qs: int = 1) -> np.nda
                               _ptr(A))
     if rc:
         raise ValueError(f"oracle_integrate failed ({rc})")
+    return A
+
+
+def integrate_coefficient(form: str, coords, conn, w, qs: int = 1) -> np.ndarray:
+    """Element matrices [E, n, n] (float64) of the Laplacian with a P1
+    coefficient w given per vertex ([N_v]): A_ij = int w grad phi_i . grad phi_j
+    (Sec. 3.1, eqs. 20-21), form "laplace_p1" or "laplace_p2"."""
+    lib = _load()
+    kind, deg = _parse(form)
+    if kind != 0:
+        raise ValueError("integrate_coefficient: Laplacian forms only")
+    dim, x, y, z = _coords_soa(coords)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    E = conn.shape[0]
+    n = local_size(form, dim)
+    wv = np.ascontiguousarray(w, dtype=np.float64)
+    if wv.shape != (x.shape[0],):
+        raise ValueError("w must hold one value per vertex")
+    A = np.empty((E, n, n))
+    rc = lib.oracle_integrate_w(deg, dim, x.shape[0], _ptr(x), _ptr(y), _ptr(z), E,
+                                _ptr(conn, ctypes.c_int32), _ptr(wv), qs, _ptr(A))
+    if rc:
+        raise ValueError(f"oracle_integrate_w failed ({rc})")
     return A
 
 

@@ -136,7 +136,7 @@ int oracle_element(int kind, int degree, int dim, const double *xv, double mu,
                    double lam, int qs, double *A, double *detv)
 {
     if (check_args(kind, degree, dim, qs)) return -1;
-    double d = element_matrix_d(kind, degree, dim, xv, mu, lam, qs, A);
+    double d = element_matrix_d(kind, degree, dim, xv, mu, lam, NULL, qs, A);
     if (detv) *detv = d;
     return 0;
 }
@@ -165,7 +165,35 @@ int oracle_integrate(int kind, int degree, int dim, int64_t nv,
             for (int al = 0; al < dim; ++al) xv[a * dim + al] = X[al][v];
         }
         double m = mu ? mu[e] : 0.0, l = lam ? lam[e] : 0.0;
-        element_matrix_d(kind, degree, dim, xv, m, l, qs, A + e * (int64_t)n * n);
+        element_matrix_d(kind, degree, dim, xv, m, l, NULL, qs, A + e * (int64_t)n * n);
+    }
+    return bad ? -2 : 0;
+}
+
+/* The Laplacian with a P1 coefficient (Sec. 3.1, eqs. 20-21):
+ *   A_ij = int_T w grad phi_i . grad phi_j,   w = sum_a w[conn[e][a]] lambda_a,
+ * for every element; w is given per vertex ([nv]).  Same layout as
+ * oracle_integrate.  The default rule (qs = 1, degree 3) is exact for P1 and
+ * P2 (integrand degree 1 and 3).                                          */
+int oracle_integrate_w(int degree, int dim, int64_t nv,
+                       const double *x, const double *y, const double *z,
+                       int64_t ne, const int32_t *conn, const double *w, int qs, double *A)
+{
+    if (check_args(ORACLE_LAPLACE, degree, dim, qs) || !w) return -1;
+    const int n = local_size(ORACLE_LAPLACE, degree, dim);
+    const double *X[3] = {x, y, z};
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|:bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double xv[12], wv[4];
+        for (int a = 0; a <= dim; ++a) {
+            int32_t v = conn[e * (dim + 1) + a];
+            if (v < 0 || v >= nv) { bad = 1; v = 0; }
+            for (int al = 0; al < dim; ++al) xv[a * dim + al] = X[al][v];
+            wv[a] = w[v];
+        }
+        element_matrix_d(ORACLE_LAPLACE, degree, dim, xv, 0.0, 0.0, wv, qs,
+                         A + e * (int64_t)n * n);
     }
     return bad ? -2 : 0;
 }
@@ -205,7 +233,7 @@ int oracle_gradient(int kind, int degree, int dim, int64_t nv,
             if (p >= 0 && p < np) xz[p] += h * I;
             if (p == np) mz += h * I;
             if (p == np + 1) lz += h * I;
-            element_matrix_z(kind, degree, dim, xz, mz, lz, qs, Az);
+            element_matrix_z(kind, degree, dim, xz, mz, lz, NULL, qs, Az);
             double _Complex L = 0.0;
             for (int k = 0; k < n * n; ++k) L += dAe[k] * Az[k];
             if (p < 0) {

@@ -100,9 +100,10 @@ def _p2_exact_reference(dim):
     return sum(K[:, :, k, k] for k in range(dim))
 
 
-def _p2_exact_tensor(dim):
+def _p2_exact_tensor(dim, weight=None):
     """K[i, j, mu, nu] = int_ref dphi_i/dxi_mu dphi_j/dxi_nu for the P2 basis on
-    the unit simplex, in exact rational arithmetic (returned as floats).
+    the unit simplex, in exact rational arithmetic (returned as floats); with
+    ``weight`` = m the integrand carries the extra factor lambda_m.
 
     grad phi_i = sum_a c_ia(lambda) grad lambda_a with c linear in lambda;
     int_ref lambda^alpha = alpha! / (|alpha| + d)!  (volume 1/d! included).
@@ -132,6 +133,8 @@ def _p2_exact_tensor(dim):
         for ea, ca in p.items():
             for eb, cb in q.items():
                 alpha = [x + y for x, y in zip(ea, eb)]
+                if weight is not None:
+                    alpha[weight] += 1
                 tot += ca * cb * Fraction(math.prod(math.factorial(x) for x in alpha),
                                           math.factorial(sum(alpha) + dim))
         return tot
@@ -421,6 +424,70 @@ def test_patch_elasticity_linear_field():
     vols = np.array([abs(np.linalg.det((X[c[1:]] - X[c[0]]).T)) / 6 for c in m.conn])
     ref = np.sum(vols * (2 * mu * np.sum(eps * eps) + lam * np.trace(eps) ** 2))
     assert np.isclose(u @ K @ u, ref, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Laplacian with a P1 coefficient (Sec. 3.1, eqs. 20-23)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("form,dim", [("laplace_p1", 2), ("laplace_p1", 3), ("laplace_p2", 2),
+                                      ("laplace_p2", 3)])
+def test_coefficient_one_is_the_laplacian(form, dim):
+    m = (meshgen.square_mesh(5, 0.2, 41, np.float64) if dim == 2
+         else meshgen.cube_mesh(2, 2, 2, 0.15, 42, np.float64))
+    A1 = oracle.integrate_coefficient(form, m.coords, m.conn, np.ones(m.n_vertices))
+    A = oracle.integrate(form, m.coords, m.conn)
+    np.testing.assert_allclose(A1, A, rtol=0, atol=1e-14 * np.abs(A).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coefficient_p1_is_mean_times_laplacian(dim):
+    """P1: grad phi constant, so int w grad phi_i . grad phi_j = mean_e(w) A_ij."""
+    m = (meshgen.square_mesh(6, 0.2, 43, np.float64) if dim == 2
+         else meshgen.cube_mesh(2, 3, 2, 0.15, 44, np.float64))
+    rng = np.random.default_rng(45)
+    w = np.exp(rng.normal(size=m.n_vertices))
+    Aw = oracle.integrate_coefficient("laplace_p1", m.coords, m.conn, w)
+    A = oracle.integrate("laplace_p1", m.coords, m.conn)
+    ref = A * w[m.conn].mean(axis=1)[:, None, None]
+    np.testing.assert_allclose(Aw, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coefficient_p2_reference_exact_rational(dim):
+    """P2 on the unit simplex with w = lambda_m (w = 1 at vertex m, 0 at the
+    others): the exact-rational K^{ij m} traced over mu = nu."""
+    for mvert in range(dim + 1):
+        K = _p2_exact_tensor(dim, weight=mvert)
+        ref = sum(K[:, :, k, k] for k in range(dim))
+        w = np.zeros(dim + 1)
+        w[mvert] = 1.0
+        A = oracle.integrate_coefficient("laplace_p2", REF[dim], np.arange(dim + 1)[None], w)[0]
+        np.testing.assert_allclose(A, ref, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("form", ["laplace_p1", "laplace_p2"])
+def test_coefficient_linear_kernel_patch_and_degree(form):
+    """Linear in w; constants in the kernel; linear u: u^T K u = |g|^2 int w; a
+    degree-7 rule agrees with the default degree-3 rule."""
+    m = meshgen.cube_mesh(2, 2, 2, 0.15, 46, np.float64)
+    rng = np.random.default_rng(47)
+    w1, w2 = np.exp(rng.normal(size=(2, m.n_vertices)))
+    A1 = oracle.integrate_coefficient(form, m.coords, m.conn, w1)
+    A2 = oracle.integrate_coefficient(form, m.coords, m.conn, w2)
+    A12 = oracle.integrate_coefficient(form, m.coords, m.conn, w1 + w2)
+    np.testing.assert_allclose(A12, A1 + A2, rtol=0, atol=1e-14 * np.abs(A12).max())
+    assert np.abs(A1.sum(axis=2)).max() <= 1e-13 * np.abs(A1).max()
+    A7 = oracle.integrate_coefficient(form, m.coords, m.conn, w1, qs=3)
+    np.testing.assert_allclose(A7, A1, rtol=0, atol=1e-13 * np.abs(A1).max())
+    if form == "laplace_p1":
+        K = _assemble(A1, m.conn, 1, m.n_vertices)
+        g = np.array([0.4, -0.9, 0.3])
+        u = m.coords @ g
+        X = m.coords
+        vols = np.array([abs(np.linalg.det((X[c[1:]] - X[c[0]]).T)) / 6 for c in m.conn])
+        ref = g @ g * np.sum(vols * w1[m.conn].mean(axis=1))
+        assert np.isclose(u @ K @ u, ref, rtol=1e-12)
 
 
 # --------------------------------------------------------------------------
