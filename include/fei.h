@@ -167,6 +167,24 @@ double fei_reference_scale(int form, int dim);
 int fei_integrate(const fei_mesh *m, int form, const float *mu, const float *lam,
                   float *A, const fei_options *opt, void *stream);
 
+/* The Laplacian with a P1 coefficient w (Sec. 3.1, eqs. 20-23):
+ *   A[e]_ij = int_e w grad phi_i . grad phi_j,   w = sum_k w_k phi_k (P1),
+ * computed as sum_k w_k G^{mu nu} K^{ijk}_{mu nu} with the arity-3 reference
+ * tensor K^{ijk} (fei_reference_tensor_coefficient) and G of eq. 8.
+ *   form     FEI_LAPLACE_P1 or FEI_LAPLACE_P2 (FEI_EUNSUPPORTED otherwise)
+ *   w        device [n_vertices] FP32: the coefficient's value at each vertex
+ *   A        device [E][n][n] FP32, 16-byte aligned, overwritten
+ *   opt      precision must be FEI_PREC_FP32; tau, counters and store_rows
+ *            (0, -1, n, or 2 where 2n is a multiple of 4) as for fei_integrate
+ * Asynchronous on `stream`.                                                 */
+int fei_integrate_coefficient(const fei_mesh *m, int form, const float *w, float *A,
+                              const fei_options *opt, void *stream);
+
+/* K^{ijk}_{mu nu} = int_ref dphi_i/dxi_mu phi_k dphi_j/dxi_nu (k over the P1
+ * coefficient's vertices) of FEI_LAPLACE_P1 / FEI_LAPLACE_P2, into HOST memory
+ * as [nb][nb][dim+1][dim][dim]; with K == NULL only *len is written.        */
+int fei_reference_tensor_coefficient(int form, int dim, float *K, int64_t *len);
+
 /* Adjoint of fei_integrate for L = sum_e <dA_e, A_e> (the reverse of the
  * chain A_e <- G_e <- (J^-1, |J|) <- vertex coordinates, Lame coefficients),
  * with G recomputed from the mesh rather than stored.

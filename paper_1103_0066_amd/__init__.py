@@ -24,7 +24,8 @@ import torch
 from . import _lib
 from ._lib import FORMS, PRECISIONS, FeiError
 
-__all__ = ["integrate", "integrate_adjoint", "element_matrices", "local_size",
+__all__ = ["integrate", "integrate_adjoint", "integrate_coefficient", "element_matrices",
+           "local_size", "reference_tensor_coefficient",
            "reference_tensor", "reference_scale", "validate_mesh", "Batch", "Assembly", "FeiError",
            "FORMS", "PRECISIONS", "library_path"]
 
@@ -150,6 +151,40 @@ def integrate(coords: torch.Tensor, conn: torch.Tensor, form: str,
     _lib.check(lib.fei_integrate(ctypes.byref(m), _form_id(form), _ptr(mu), _ptr(lam),
                                  _ptr(out), ctypes.byref(o), _stream(dev)))
     return out
+
+
+def integrate_coefficient(coords: torch.Tensor, conn: torch.Tensor, form: str, w: torch.Tensor, *,
+                          tau: float = 100.0, counters: Optional[torch.Tensor] = None,
+                          out: Optional[torch.Tensor] = None, store_rows: int = 0) -> torch.Tensor:
+    """Element matrices of the Laplacian with a P1 coefficient ``w`` ([N_v]
+    float32, its value at each vertex): A_ij = int w grad phi_i . grad phi_j
+    (fei_integrate_coefficient; form "laplace_p1" or "laplace_p2")."""
+    lib = _lib.load()
+    m = _mesh(coords, conn)
+    dev = coords.device
+    n = local_size(form, m.dim)
+    _require(w, "w", torch.float32, dev, (m.n_vertices,))
+    if out is None:
+        out = torch.empty((m.n_elements, n, n), dtype=torch.float32, device=dev)
+    else:
+        _require(out, "out", torch.float32, dev, (m.n_elements, n, n))
+    o = _options("fp32", tau, counters, store_rows)
+    _lib.check(lib.fei_integrate_coefficient(ctypes.byref(m), _form_id(form), _ptr(w), _ptr(out),
+                                             ctypes.byref(o), _stream(dev)))
+    return out
+
+
+def reference_tensor_coefficient(form: str, dim: int) -> np.ndarray:
+    """K^{ijk}_{mu nu} [nb, nb, dim+1, dim, dim] of the Laplacian with a P1
+    coefficient (host-only)."""
+    lib = _lib.load()
+    n = ctypes.c_int64()
+    _lib.check(lib.fei_reference_tensor_coefficient(_form_id(form), dim, None, ctypes.byref(n)))
+    K = np.zeros(n.value, dtype=np.float32)
+    _lib.check(lib.fei_reference_tensor_coefficient(_form_id(form), dim, K.ctypes.data,
+                                                    ctypes.byref(n)))
+    nb = int(round((n.value / (dim + 1) / dim / dim) ** 0.5))
+    return K.reshape(nb, nb, dim + 1, dim, dim)
 
 
 def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: torch.Tensor,

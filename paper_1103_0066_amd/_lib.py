@@ -24,7 +24,8 @@ ABI_VERSION = 2          # FEI_ABI_VERSION of the structs below
 
 EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_default",
            "fei_local_size", "fei_reference_tensor", "fei_reference_scale", "fei_integrate",
-           "fei_integrate_adjoint", "fei_integrate_adjoint_det", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
+           "fei_integrate_adjoint", "fei_integrate_adjoint_det", "fei_integrate_coefficient",
+           "fei_reference_tensor_coefficient", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
            "fei_batch_run_adjoint", "fei_batch_tune", "fei_batch_get_config", "fei_batch_set_config",
            "fei_batch_copy_incidence", "fei_batch_destroy", "fei_assembly_create",
            "fei_assembly_info", "fei_assembly_copy_pattern", "fei_assemble",
@@ -103,6 +104,10 @@ def load():
                                           f32p, f32p, f32p, f32p, f32p, f32p,
                                           ctypes.POINTER(FeiOptions), vp]
     lib.fei_integrate_adjoint_det.argtypes = lib.fei_integrate_adjoint.argtypes
+    lib.fei_integrate_coefficient.argtypes = [ctypes.POINTER(FeiMesh), ctypes.c_int, f32p, f32p,
+                                              ctypes.POINTER(FeiOptions), vp]
+    lib.fei_reference_tensor_coefficient.argtypes = [ctypes.c_int, ctypes.c_int, vp,
+                                                     ctypes.POINTER(i64)]
     lib.fei_validate_mesh.argtypes = [ctypes.POINTER(FeiMesh), ctypes.POINTER(i64), vp]
     lib.fei_batch_create.argtypes = [ctypes.POINTER(FeiBatchItem), ctypes.c_int,
                                      ctypes.POINTER(FeiOptions), ctypes.POINTER(vp)]

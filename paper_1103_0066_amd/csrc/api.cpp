@@ -346,11 +346,67 @@ int fei_integrate(const fei_mesh *m, int form, const float *mu, const float *lam
     p.m = mv;
     p.mu = mu;
     p.lam = lam;
+    p.w = nullptr;
     p.A = A;
     p.counters = o.counters;
     p.tau2 = tau2_of(o.tau);
     hipError_t e = launch(p, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return FEI_OK;
+}
+
+int fei_integrate_coefficient(const fei_mesh *m, int form, const float *w, float *A,
+                              const fei_options *opt, void *stream)
+{
+    MeshView mv;
+    int rc = check_mesh(m, mv);
+    if (rc) return rc;
+    if (form != FEI_LAPLACE_P1 && form != FEI_LAPLACE_P2)
+        return fail(valid_form(form) ? FEI_EUNSUPPORTED : FEI_EINVAL,
+                    "a P1 coefficient is taken by the Laplacian forms (form %d)", form);
+    fei_options o = opt ? *opt : defaults();
+    if ((rc = check_options(o))) return rc;
+    if (m->n_elements == 0) return FEI_OK;
+    if (!w || !aligned(w, 4)) return fail(FEI_EINVAL, "w NULL or misaligned");
+    if (!A) return fail(FEI_EINVAL, "A is NULL");
+    if (!aligned(A, 16)) return fail(FEI_EINVAL, "A must be 16-byte aligned");
+    const Variant v{form == FEI_LAPLACE_P1 ? int(WLAP1) : int(WLAP2), m->dim,
+                    m->coord_dtype == FEI_F64, o.precision, o.store_rows, 0};
+    FwdLauncher launch = find_forward_coefficient(v);
+    if (!launch)
+        return fail(FEI_EUNSUPPORTED, "no kernel for this variant (the contraction is FP32; "
+                                      "store_rows 0, -1, n or 2)");
+    FwdParams p;
+    p.m = mv;
+    p.mu = nullptr;
+    p.lam = nullptr;
+    p.w = w;
+    p.A = A;
+    p.counters = o.counters;
+    p.tau2 = tau2_of(o.tau);
+    hipError_t e = launch(p, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return FEI_OK;
+}
+
+int fei_reference_tensor_coefficient(int form, int dim, float *K, int64_t *len)
+{
+    if (!len) return fail(FEI_EINVAL, "len is NULL");
+    if ((form != FEI_LAPLACE_P1 && form != FEI_LAPLACE_P2) || (dim != 2 && dim != 3))
+        return fail(FEI_EINVAL, "bad form %d or dim %d", form, dim);
+    const int F = form == FEI_LAPLACE_P1 ? WLAP1 : WLAP2;
+    const int nb = form == FEI_LAPLACE_P1 ? dim + 1 : (dim + 1) * (dim + 2) / 2;
+    const int kden = form == FEI_LAPLACE_P1 ? dim + 1 : (dim + 1) * (dim + 2) * (dim + 3);
+    const double scale = 1.0 / (double(dim == 2 ? 2 : 6) * kden);
+    *len = int64_t(nb) * nb * (dim + 1) * dim * dim;
+    if (!K) return FEI_OK;
+    int64_t t = 0;
+    for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j)
+            for (int k = 0; k <= dim; ++k)
+                for (int mu = 0; mu < dim; ++mu)
+                    for (int nu = 0; nu < dim; ++nu)
+                        K[t++] = float(double(kwblock(F, dim, i, j, k, mu, nu)) * scale);
     return FEI_OK;
 }
 

@@ -9,6 +9,7 @@
 #include "assemble.h"
 #include "batch_dev.h"
 #include "gather.h"
+#include "fwd_coef.h"
 #include "fwd_fma.h"
 #include "fwd_mfma.h"
 
@@ -252,6 +253,49 @@ FwdLauncher find_forward(const Variant &v)
         }
     }
     return nullptr;
+}
+
+namespace {
+
+template <int F, int D, typename CT, int R>
+hipError_t launch_fwd_coef(const FwdParams &p, hipStream_t s)
+{
+    const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((fwd_coef_kernel<F, D, CT, R>), dim3(unsigned(n_groups)), dim3(kBlock), 0,
+                       s, p);
+    return hipGetLastError();
+}
+
+template <int F, int D, typename CT>
+FwdLauncher fwd_coef_rows(int rows)
+{
+    constexpr int N = Traits<F, D>::N;
+    const int r = resolve_rows(rows, N);
+    if (r == N) return &launch_fwd_coef<F, D, CT, N>;
+    if (r == 0) return &launch_fwd_coef<F, D, CT, 0>;
+    if constexpr (N % 2 == 0 && (2 * N) % 4 == 0)
+        if (r == 2) return &launch_fwd_coef<F, D, CT, 2>;
+    return nullptr;
+}
+
+template <int F, int D>
+FwdLauncher fwd_coef_for(const Variant &v)
+{
+    if (v.precision != P_FP32) return nullptr;
+    return v.coord_f64 ? fwd_coef_rows<F, D, double>(v.rows) : fwd_coef_rows<F, D, float>(v.rows);
+}
+
+}  // namespace
+
+FwdLauncher find_forward_coefficient(const Variant &v)
+{
+    switch (v.form * 4 + v.dim) {
+    case WLAP1 * 4 + 2: return fwd_coef_for<WLAP1, 2>(v);
+    case WLAP1 * 4 + 3: return fwd_coef_for<WLAP1, 3>(v);
+    case WLAP2 * 4 + 2: return fwd_coef_for<WLAP2, 2>(v);
+    case WLAP2 * 4 + 3: return fwd_coef_for<WLAP2, 3>(v);
+    default: return nullptr;
+    }
 }
 
 AdjLauncher find_adjoint(const Variant &v)

@@ -18,6 +18,7 @@ struct MeshView {
 struct FwdParams {
     MeshView m;
     const float *mu, *lam;     // elasticity only
+    const float *w;            // forms with a P1 coefficient: [n_vertices]
     float *A;                  // [E][n][n]
     int32_t *counters;         // optional [2]
     float tau2;                // squared quality threshold; < 0 forces FP64
@@ -50,6 +51,8 @@ using AdjLauncher = hipError_t (*)(const AdjParams &, hipStream_t);
 
 // Returns NULL when no kernel exists for the variant.
 FwdLauncher find_forward(const Variant &v);
+// Forms with a P1 coefficient (v.form WLAP1 or WLAP2; FP32 contraction).
+FwdLauncher find_forward_coefficient(const Variant &v);
 AdjLauncher find_adjoint(const Variant &v);
 
 // Heterogeneous batch: one work item per (mesh, form), laid out for the

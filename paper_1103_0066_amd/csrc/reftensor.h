@@ -23,17 +23,29 @@
 
 namespace fei {
 
-enum Form { LAP1 = 1, ELA1 = 2, LAP2 = 3 };
+// WLAP1, WLAP2: the Laplacian with a P1 coefficient w (Sec. 3.1, eqs. 20-23),
+// whose reference tensor K^{ijk}_{mu nu} has a third index k over the
+// coefficient's nodal values.
+enum Form { LAP1 = 1, ELA1 = 2, LAP2 = 3, WLAP1 = 4, WLAP2 = 5 };
+
+FEI_HD constexpr bool is_p2(int form) { return form == LAP2 || form == WLAP2; }
+FEI_HD constexpr bool has_coefficient(int form) { return form == WLAP1 || form == WLAP2; }
 
 template <int FORM, int DIM>
 struct Traits {
     static constexpr int NV = DIM + 1;                                   // vertices
-    static constexpr int NB = (FORM == LAP2) ? (DIM + 1) * (DIM + 2) / 2 : DIM + 1;  // scalar basis
+    static constexpr int NB = is_p2(FORM) ? (DIM + 1) * (DIM + 2) / 2 : DIM + 1;  // scalar basis
     static constexpr int NC = (FORM == ELA1) ? DIM : 1;                  // components
     static constexpr int N = NB * NC;                                    // element matrix side
     static constexpr int GD = NC * DIM;                                  // geometric tensor side
     static constexpr int G = GD * (GD + 1) / 2;                          // its unique entries
-    static constexpr int KDEN = (FORM == LAP2) ? (DIM + 1) * (DIM + 2) : 1;
+    // K = Kp * vol_ref / KDEN with integer Kp: the degree of the integrand's
+    // barycentric polynomial sets KDEN (int lambda^alpha / vol_ref has
+    // denominator (d+1)...(d+|alpha|))
+    static constexpr int KDEN = (FORM == LAP2)    ? (DIM + 1) * (DIM + 2)
+                                : (FORM == WLAP1) ? (DIM + 1)
+                                : (FORM == WLAP2) ? (DIM + 1) * (DIM + 2) * (DIM + 3)
+                                                  : 1;
     static constexpr int FACT = (DIM == 2) ? 2 : 6;                      // d! = 1 / vol_ref
     // Gf = SCALE * |det J| * (J^-1 J^-T, or its Lame analogue)
     static constexpr double SCALE = 1.0 / (double(FACT) * double(KDEN));
@@ -81,6 +93,37 @@ FEI_HD constexpr int p2_mass(int dim, int i, int a, int j, int b)
         for (int l = 0; l <= dim; ++l)
             s += p2_lin(dim, i, a, k) * p2_lin(dim, j, b, l) * (1 + (k == l));
     }
+    return s;
+}
+
+// KDEN/vol * int_ref c_ia c_jb lambda_m with KDEN = (d+1)(d+2)(d+3), using
+// int lambda^alpha / vol = alpha! d! / (|alpha| + d)!:
+//   lambda_m -> (d+2)(d+3),  lambda_k lambda_m -> (1 + delta_km)(d+3),
+//   lambda_k lambda_l lambda_m -> alpha! (6, 2 or 1 by the multiplicities).
+FEI_HD constexpr int p2_mass_w(int dim, int i, int a, int j, int b, int m)
+{
+    const int c0 = p2_lin(dim, i, a, -1), d0 = p2_lin(dim, j, b, -1);
+    int s = c0 * d0 * (dim + 2) * (dim + 3);
+    for (int k = 0; k <= dim; ++k)
+        s += (c0 * p2_lin(dim, j, b, k) + d0 * p2_lin(dim, i, a, k)) * (1 + (k == m)) * (dim + 3);
+    for (int k = 0; k <= dim; ++k)
+        for (int l = 0; l <= dim; ++l) {
+            const int f = (k == l && l == m) ? 6 : ((k == l || l == m || k == m) ? 2 : 1);
+            s += p2_lin(dim, i, a, k) * p2_lin(dim, j, b, l) * f;
+        }
+    return s;
+}
+
+// Integer coefficient tensor Kp^{ijm}_{mu nu} = KDEN/vol int_ref dphi_i/dxi_mu
+// lambda_m dphi_j/dxi_nu of the forms with a P1 coefficient (eq. 23's K^{ijk}).
+// P1: the gradients are constant and int lambda_m / vol = 1/(d+1) = 1/KDEN.
+FEI_HD constexpr int kwblock(int form, int dim, int i, int j, int m, int mu, int nu)
+{
+    if (form == WLAP1) return gref(i, mu) * gref(j, nu);
+    int s = 0;
+    for (int a = 0; a <= dim; ++a)
+        for (int b = 0; b <= dim; ++b)
+            s += gref(a, mu) * gref(b, nu) * p2_mass_w(dim, i, a, j, b, m);
     return s;
 }
 

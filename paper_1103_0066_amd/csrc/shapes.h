@@ -41,6 +41,12 @@ struct FragTable {
 // entries (flat element-matrix index, integer coefficient), padded with
 // zero coefficients to NNZ.  U_g = sum_t coef[g][t] * dA[ij[g][t]] is the
 // folded K^T applied to dA.
+// Coefficient reference tensor [NB][NB][NV][DIM][DIM] (integer values, as float).
+template <int FORM, int DIM>
+struct KWTable {
+    float v[Traits<FORM, DIM>::NB * Traits<FORM, DIM>::NB * (DIM + 1) * DIM * DIM];
+};
+
 template <int FORM, int DIM>
 struct KSparseShape {
     static constexpr int NNZ = (FORM == LAP2) ? ((DIM == 3) ? 72 : 32) : 8;
