@@ -67,6 +67,10 @@ def _load():
     lib.oracle_integrate_w.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp, dp,
                                        ctypes.c_int64, ip, dp, ctypes.c_int, dp]
     lib.oracle_integrate_w.restype = ctypes.c_int
+    lib.oracle_integrate_general.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int64, dp, dp, dp, ctypes.c_int64, ip,
+                                             ctypes.c_int, dp, dp, ctypes.c_int, dp]
+    lib.oracle_integrate_general.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -165,6 +169,34 @@ def integrate_coefficient(form: str, coords, conn, w, qs: int = 1) -> np.ndarray
                                 _ptr(conn, ctypes.c_int32), _ptr(wv), qs, _ptr(A))
     if rc:
         raise ValueError(f"oracle_integrate_w failed ({rc})")
+    return A
+
+
+def integrate_general(degree: int, ncomp: int, W, coords, conn, coefs=(), qs: int = 2):
+    """Element matrices [E, n, n] of a general bilinear form of Lagrange
+    elements: A_{(i,c),(j,d)} = int sum_{a,b} C[(a,c),(b,d)] D_a phi_i D_b phi_j,
+    D_0 the value, D_{1+alpha} = d/dx_alpha, C = W[0] + sum_k coefs[k][e] W[k+1].
+    W: [n_coef + 1, m, m] with m = (dim + 1) * ncomp, index a * ncomp + c.
+    The default rule (qs = 2, degree 5) is exact for P2 mass terms (degree 4)."""
+    lib = _load()
+    dim, x, y, z = _coords_soa(coords)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    E = conn.shape[0]
+    nb = dim + 1 if degree == 1 else (dim + 1) * (dim + 2) // 2
+    n = ncomp * nb
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    m = (dim + 1) * ncomp
+    if W.ndim != 3 or W.shape[1:] != (m, m):
+        raise ValueError(f"W must be [n_coef + 1, {m}, {m}]")
+    n_coef = W.shape[0] - 1
+    cf = np.ascontiguousarray(np.reshape(coefs, (n_coef, E)) if n_coef else np.zeros(1),
+                              dtype=np.float64)
+    A = np.empty((E, n, n))
+    rc = lib.oracle_integrate_general(degree, dim, ncomp, x.shape[0], _ptr(x), _ptr(y), _ptr(z),
+                                      E, _ptr(conn, ctypes.c_int32), n_coef, _ptr(W), _ptr(cf),
+                                      qs, _ptr(A))
+    if rc:
+        raise ValueError(f"oracle_integrate_general failed ({rc})")
     return A
 
 

@@ -198,6 +198,95 @@ int oracle_integrate_w(int degree, int dim, int64_t nv,
     return bad ? -2 : 0;
 }
 
+/* Values of the scalar basis at barycentric point bc (P1: lambda_a; P2: vertex
+ * a: lambda_a (2 lambda_a - 1); edge (a,b): 4 lambda_a lambda_b, edges in the
+ * order of basis_gradients).                                               */
+static void basis_values(int degree, int dim, const double *bc, double *phi)
+{
+    const int nv = dim + 1;
+    if (degree == 1) {
+        for (int a = 0; a < nv; ++a) phi[a] = bc[a];
+        return;
+    }
+    for (int a = 0; a < nv; ++a) phi[a] = bc[a] * (2.0 * bc[a] - 1.0);
+    int e = nv;
+    for (int a = 0; a < nv; ++a)
+        for (int b = a + 1; b < nv; ++b, ++e) phi[e] = 4.0 * bc[a] * bc[b];
+}
+
+/* A general bilinear form of Lagrange elements (degree 1 or 2, ncomp = 1 or
+ * dim components, node-major DOFs I = ncomp * i + c):
+ *
+ *   A_{(i,c),(j,d)} = int_T sum_{a,b} C[(a,c),(b,d)] D_a phi_i D_b phi_j,
+ *
+ * with D_0 = the value and D_{1+alpha} = d/dx_alpha (physical derivatives),
+ * C[(a,c),(b,d)] = W_0 + sum_k coef_k(e) W_k a per-element combination of
+ * the tables W ([n_coef + 1][m][m], m = (dim + 1) * ncomp, index a * ncomp + c).
+ * This is the plain definition of the forms a form language describes
+ * (Sec. 3.2): quadrature on the physical element, physical gradients from
+ * the Vandermonde inverse, no reference tensor.  coef: [n_coef][ne].      */
+int oracle_integrate_general(int degree, int dim, int ncomp, int64_t nv,
+                             const double *x, const double *y, const double *z,
+                             int64_t ne, const int32_t *conn, int n_coef, const double *W,
+                             const double *coef, int qs, double *A)
+{
+    if ((degree != 1 && degree != 2) || (dim != 2 && dim != 3) ||
+        (ncomp != 1 && ncomp != dim) || n_coef < 0 || n_coef > 8 || qs < 0 || qs > 4)
+        return -1;
+    const int nvert = dim + 1;
+    const int nb = (degree == 1) ? nvert : nvert * (nvert + 1) / 2;
+    const int n = ncomp * nb;
+    const int m = (dim + 1) * ncomp;
+    const double *X[3] = {x, y, z};
+    double pts[ORACLE_MAX_QP][4], w[ORACLE_MAX_QP];
+    const int nq = oracle_gm_rule(dim, qs, pts, w);
+    if (nq < 0) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|:bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double V[4][4], Cv[4][4], gl[4][3];
+        for (int a = 0; a < nvert; ++a) {
+            int32_t v = conn[e * nvert + a];
+            if (v < 0 || v >= nv) { bad = 1; v = 0; }
+            V[a][0] = 1.0;
+            for (int al = 0; al < dim; ++al) V[a][1 + al] = X[al][v];
+        }
+        const double detV = vandermonde_inverse_d(nvert, V, Cv);
+        const double absdet = detV < 0.0 ? -detV : detV;
+        for (int a = 0; a < nvert; ++a)
+            for (int al = 0; al < dim; ++al) gl[a][al] = Cv[1 + al][a];
+        double C[36 * 36];
+        for (int t = 0; t < m * m; ++t) {
+            double c = W[t];
+            for (int k = 0; k < n_coef; ++k) c += coef[k * ne + e] * W[(size_t)(k + 1) * m * m + t];
+            C[t] = c;
+        }
+        double *Ae = A + e * (int64_t)n * n;
+        for (int t = 0; t < n * n; ++t) Ae[t] = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            double g[10][3], phi[10], D[4][10];
+            basis_gradients_d(degree, dim, pts[q], gl, g);
+            basis_values(degree, dim, pts[q], phi);
+            for (int i = 0; i < nb; ++i) {
+                D[0][i] = phi[i];
+                for (int al = 0; al < dim; ++al) D[1 + al][i] = g[i][al];
+            }
+            const double wq = w[q] * absdet;
+            for (int i = 0; i < nb; ++i)
+                for (int c = 0; c < ncomp; ++c)
+                    for (int j = 0; j < nb; ++j)
+                        for (int d = 0; d < ncomp; ++d) {
+                            double s = 0.0;
+                            for (int a = 0; a <= dim; ++a)
+                                for (int b = 0; b <= dim; ++b)
+                                    s += C[(a * ncomp + c) * m + b * ncomp + d] * D[a][i] * D[b][j];
+                            Ae[(ncomp * i + c) * n + ncomp * j + d] += wq * s;
+                        }
+        }
+    }
+    return bad ? -2 : 0;
+}
+
 /* Complex-step gradient of L_e = sum_IJ dA_e[I][J] A_e[I][J] for each element.
  *   gvert: [ne][dim+1][dim]  dL_e / d x_{conn[e][a]}[alpha]
  *   gmu, glam: [ne] or NULL  dL_e / d mu_e, dL_e / d lambda_e

@@ -491,6 +491,95 @@ def test_coefficient_linear_kernel_patch_and_degree(form):
 
 
 # --------------------------------------------------------------------------
+# General bilinear forms (the plain definition a form language describes)
+# --------------------------------------------------------------------------
+
+def _W_laplace(dim):
+    W = np.zeros((1, dim + 1, dim + 1))
+    for a in range(dim):
+        W[0, 1 + a, 1 + a] = 1.0
+    return W
+
+
+def _W_elasticity(dim):
+    """[const, mu, lambda] tables of 2 mu eps(u):eps(v) + lambda div u div v,
+    index (direction a, component c) -> a * dim + c, direction 0 = value."""
+    m = (dim + 1) * dim
+    W = np.zeros((3, m, m))
+    for al in range(dim):
+        for c in range(dim):
+            for be in range(dim):
+                for d in range(dim):
+                    i, j = (1 + al) * dim + c, (1 + be) * dim + d
+                    W[1, i, j] = (c == d) * (al == be) + (al == d) * (be == c)
+                    W[2, i, j] = (al == c) * (be == d)
+    return W
+
+
+@pytest.mark.parametrize("degree,dim", [(1, 2), (1, 3), (2, 2), (2, 3)])
+def test_general_form_reproduces_laplacian_and_elasticity(degree, dim):
+    m = (meshgen.square_mesh(4, 0.2, 51, np.float64) if dim == 2
+         else meshgen.cube_mesh(2, 2, 1, 0.15, 52, np.float64))
+    A = oracle.integrate_general(degree, 1, _W_laplace(dim), m.coords, m.conn)
+    Ao = oracle.integrate(f"laplace_p{degree}", m.coords, m.conn)
+    np.testing.assert_allclose(A, Ao, rtol=0, atol=1e-13 * np.abs(Ao).max())
+    mu, lam = meshgen.lame(m.n_elements, 53)
+    A = oracle.integrate_general(degree, dim, _W_elasticity(dim), m.coords, m.conn,
+                                 np.stack([mu, lam]))
+    Ao = oracle.integrate(f"elastic_p{degree}", m.coords, m.conn, mu, lam)   # Voigt B^T D B
+    np.testing.assert_allclose(A, Ao, rtol=0, atol=1e-13 * np.abs(Ao).max())
+
+
+@pytest.mark.parametrize("degree,dim", [(1, 2), (1, 3), (2, 2), (2, 3)])
+def test_general_form_mass_matrix_exact_rational(degree, dim):
+    """int_ref phi_i phi_j on the unit simplex, from exact barycentric integrals."""
+    W = np.zeros((1, dim + 1, dim + 1))
+    W[0, 0, 0] = 1.0
+    A = oracle.integrate_general(degree, 1, W, REF[dim], np.arange(dim + 1)[None])[0]
+    nv = dim + 1
+    # basis as barycentric polynomials {exponent tuple: coefficient}
+    def mono(*idx):
+        e = [0] * nv
+        for k in idx:
+            e[k] += 1
+        return tuple(e)
+    basis = [{mono(a, a): Fraction(2), mono(a): Fraction(-1)} if degree == 2 else {mono(a): Fraction(1)}
+             for a in range(nv)]
+    if degree == 2:
+        basis += [{mono(a, b): Fraction(4)} for a in range(nv) for b in range(a + 1, nv)]
+    def integ(p, q):
+        tot = Fraction(0)
+        for ea, ca in p.items():
+            for eb, cb in q.items():
+                al = [x + y for x, y in zip(ea, eb)]
+                tot += ca * cb * Fraction(math.prod(math.factorial(x) for x in al),
+                                          math.factorial(sum(al) + dim))
+        return tot
+    ref = np.array([[float(integ(p, q)) for q in basis] for p in basis])
+    np.testing.assert_allclose(A, ref, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_general_form_value_derivative_p1_closed_form(dim):
+    """int (b . grad u) v + (b . grad v) u for P1: grad lambda constant and
+    int lambda_i = vol / (d + 1), so A_ij = vol/(d+1) (b.g_j + b.g_i)."""
+    rng = np.random.default_rng(54)
+    b = rng.normal(size=dim)
+    W = np.zeros((1, dim + 1, dim + 1))
+    W[0, 0, 1:] = b
+    W[0, 1:, 0] = b
+    for _ in range(5):
+        x = _random_simplex(rng, dim)
+        A = oracle.integrate_general(1, 1, W, x, np.arange(dim + 1)[None])[0]
+        V = np.hstack([np.ones((dim + 1, 1)), x])
+        G = np.linalg.inv(V)[1:].T                       # grad lambda_a, [a][alpha]
+        vol = abs(np.linalg.det(V)) / math.factorial(dim)
+        bg = G @ b
+        ref = vol / (dim + 1) * (bg[None, :] + bg[:, None])
+        np.testing.assert_allclose(A, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+# --------------------------------------------------------------------------
 # Global assembly (sparse), pinned by dense loops, energy and kernel
 # --------------------------------------------------------------------------
 
