@@ -8,9 +8,9 @@ import torch
 # its stated bound 3e-5; BF16x3 (about 24 bits) to 1e-5.
 TOL = {"fp32": 1e-5, "fp16x2": 1e-5, "bf16x2": 3e-5, "bf16x3": 1e-5}
 
-# Adjoint: vertex gradients are sums of ~24 partially cancelling FP32 terms
-# added by atomics, judged against the sum of the magnitudes of the terms (the
-# FP32 bound of the forward applies: measured errors stay below 2e-6);
+# Adjoint: vertex gradients are sums of ~24 partially cancelling FP32 terms,
+# judged against the sum of the norms of the incident elements' gradients (the
+# normwise FP32 bound of the forward, per element);
 # per-element coefficient gradients against the element's own scale.
 TOL_VERTEX = 1e-5
 TOL_COEFF = 1e-5
@@ -43,9 +43,15 @@ def element_errors(A_gpu: np.ndarray, A_orc: np.ndarray) -> np.ndarray:
 
 
 def vertex_scale(gvert: np.ndarray, conn: np.ndarray, n_vertices: int) -> np.ndarray:
-    """Per vertex: sum over incident elements of |per-element contribution| (max over
-    components), the natural scale of an atomically accumulated vertex gradient."""
-    mag = np.abs(gvert).max(axis=2)                      # [E, dim+1]
+    """Per vertex: the sum, over its incident elements, of that element's gradient
+    norm (max over all its vertices and components of |per-element contribution|).
+
+    Normwise per element, as the forward's element matrices are judged: an FP32
+    element gradient is accurate relative to its largest entry, and the
+    contribution to vertex 0 is minus the sum of the other columns of J-bar, so on
+    a near-degenerate element it is a cancelled small difference of large
+    numbers whose own magnitude is no scale for its rounding."""
+    mag = np.abs(gvert).reshape(len(gvert), -1).max(axis=1)          # [E]
     s = np.zeros(n_vertices)
-    np.add.at(s, conn.ravel(), mag.ravel())
+    np.add.at(s, conn.ravel(), np.repeat(mag, conn.shape[1]))
     return s

@@ -43,15 +43,21 @@ def _to_csr(asm, rowptr, colidx, values):
 
 
 def _scale(form, coords, conn, mu, lam, nrows_scalar):
-    """Per stored entry: the sum of |element contributions| (the bound's scale)."""
-    A = np.abs(oracle.integrate(form, coords, conn, mu, lam))
+    """Per stored entry: the sum, over the elements whose matrices add into it, of
+    that element matrix's norm max_ij |A_e,ij| -- the normwise FP32 bound of each
+    element matrix summed over the entry's terms (never zero for a stored entry;
+    an entry's own terms may cancel, or vanish exactly on a right-angled element)."""
+    A = oracle.integrate(form, coords, conn, mu, lam)
+    E = len(conn)
+    nrm = np.abs(A).reshape(E, -1).max(axis=1)
     nc = coords.shape[1] if form == "elastic_p1" else 1
     conn = conn.astype(np.int64)
-    dofs = (nc * conn[:, :, None] + np.arange(nc)).reshape(conn.shape[0], -1)
+    dofs = (nc * conn[:, :, None] + np.arange(nc)).reshape(E, -1)
     n = dofs.shape[1]
-    r = np.broadcast_to(dofs[:, :, None], (len(conn), n, n)).ravel()
-    c = np.broadcast_to(dofs[:, None, :], (len(conn), n, n)).ravel()
-    S = sp.coo_matrix((A.ravel(), (r, c)), shape=(nrows_scalar,) * 2).tocsr()
+    r = np.broadcast_to(dofs[:, :, None], (E, n, n)).ravel()
+    c = np.broadcast_to(dofs[:, None, :], (E, n, n)).ravel()
+    v = np.broadcast_to(nrm[:, None, None], (E, n, n)).ravel()
+    S = sp.coo_matrix((v, (r, c)), shape=(nrows_scalar,) * 2).tocsr()
     S.sum_duplicates()
     S.sort_indices()
     return S

@@ -6,7 +6,7 @@ import torch
 
 import meshgen
 import oracle
-from gpu_util import TOL, TOL_VERTEX, element_errors, vertex_scale
+from gpu_util import TOL, TOL_COEFF, TOL_VERTEX, element_errors, vertex_scale
 
 pytestmark = pytest.mark.gpu
 
