@@ -215,6 +215,25 @@ int fei_integrate_adjoint_det(const fei_mesh *m, int form, const float *mu,
                               float *dz, float *dmu, float *dlam,
                               const fei_options *opt, void *stream);
 
+/* fei_integrate_adjoint_det for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, same results (bit for bit), but the workspace
+ * lives in a fixed device array of the library, FEI_NOALLOC_SCRATCH_BYTES
+ * bytes, one per device, held from its first use until the process ends; the
+ * call allocates and frees nothing.  The workspace of a mesh is
+ * 4 (N_v + 1) + 4 N_v + 4 (dim + 1) E + 4 dim^2 E bytes (each part rounded up
+ * to 256; the 3D elasticity workload of 1,572,864 tets and 290,353 vertices
+ * needs 84 MB): FEI_EINVAL if that exceeds FEI_NOALLOC_SCRATCH_BYTES.
+ * `stream` must belong to the current device.  Every call on one device
+ * shares that device's array, which keeps the last call's contents: calls
+ * whose work overlaps on one device (other streams, other threads) race and
+ * must be ordered by the caller.                                            */
+#define FEI_NOALLOC_SCRATCH_BYTES (96u * 1024u * 1024u)
+int fei_integrate_adjoint_det_noalloc(const fei_mesh *m, int form, const float *mu,
+                                      const float *lam, const float *dA, float *dx, float *dy,
+                                      float *dz, float *dmu, float *dlam,
+                                      const fei_options *opt, void *stream);
+
 /* Checks conn against n_vertices on the device and returns the number of
  * out-of-range entries in *n_bad.  Synchronises the stream.                 */
 int fei_validate_mesh(const fei_mesh *m, int64_t *n_bad, void *stream);

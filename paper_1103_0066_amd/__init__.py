@@ -192,13 +192,18 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
                       tau: float = 100.0, dcoords: Optional[torch.Tensor] = None,
                       coeff_grads: bool = True, counters: Optional[torch.Tensor] = None,
                       dmu: Optional[torch.Tensor] = None, dlam: Optional[torch.Tensor] = None,
-                      store_rows: int = 0, deterministic: bool = False):
+                      store_rows: int = 0, deterministic: bool = False,
+                      no_alloc: bool = False):
     """Gradients of L = sum_e <dA_e, A_e>.
 
     Returns (dcoords [dim, N_v] float32, accumulated into ``dcoords`` when given,
     dmu [E] or None, dlam [E] or None; written into ``dmu``/``dlam`` when given).
     ``deterministic`` sums the vertex gradients in an order fixed by the mesh
-    (fei_integrate_adjoint_det: same bits on every call; FP32 coordinates)."""
+    (fei_integrate_adjoint_det: same bits on every call; FP32 coordinates).
+    ``no_alloc`` (with ``deterministic``) keeps that path's workspace in the
+    library's fixed per-device array instead of allocating it
+    (fei_integrate_adjoint_det_noalloc; at most FEI_NOALLOC_SCRATCH_BYTES of
+    workspace; calls that overlap on one device race)."""
     lib = _lib.load()
     m = _mesh(coords, conn)
     dev = coords.device
@@ -221,12 +226,16 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
     else:
         dmu = dlam = None
     o = _options("fp32", tau, counters, store_rows)
-    entry = lib.fei_integrate_adjoint_det if deterministic else lib.fei_integrate_adjoint
-    _lib.check(entry(
-        ctypes.byref(m), _form_id(form), _ptr(mu), _ptr(lam), _ptr(dA),
-        dcoords[0].data_ptr(), dcoords[1].data_ptr(),
-        dcoords[2].data_ptr() if m.dim == 3 else None, _ptr(dmu), _ptr(dlam),
-        ctypes.byref(o), _stream(dev)))
+    if no_alloc and not deterministic:
+        raise ValueError("no_alloc applies to the deterministic adjoint")
+    entry = (lib.fei_integrate_adjoint_det_noalloc if no_alloc else
+             lib.fei_integrate_adjoint_det if deterministic else lib.fei_integrate_adjoint)
+    with torch.cuda.device(dev):
+        _lib.check(entry(
+            ctypes.byref(m), _form_id(form), _ptr(mu), _ptr(lam), _ptr(dA),
+            dcoords[0].data_ptr(), dcoords[1].data_ptr(),
+            dcoords[2].data_ptr() if m.dim == 3 else None, _ptr(dmu), _ptr(dlam),
+            ctypes.byref(o), _stream(dev)))
     return dcoords, dmu, dlam
 
 

@@ -275,3 +275,36 @@ def test_coefficient_entry_point_rejects_without_device_work():
                                          None) == _lib.FEI_OK
     assert lib.fei_integrate_coefficient(ctypes.byref(m), 9, None, None, ctypes.byref(o),
                                          None) == _lib.FEI_EINVAL
+
+
+def _det_workspace(dim, E, nv):
+    up = lambda b: (b + 255) // 256 * 256
+    return up(4 * (nv + 1)) + up(4 * nv) + up(4 * (dim + 1) * E) + up(4 * dim * dim * E)
+
+
+def test_noalloc_adjoint_rejects_oversized_meshes_without_device_work():
+    """The allocation-free deterministic adjoint refuses a mesh whose workspace
+    exceeds its fixed array (checked on the host before any HIP call), and the
+    deterministic path's other limits, with FEI_EINVAL / FEI_EUNSUPPORTED."""
+    lib = _lib.load()
+    cap = _lib.NOALLOC_SCRATCH_BYTES
+    # 3D, 300,000 vertices: the smallest element count (in steps of 1,000) over the cap
+    nv = 300000
+    E = next(e for e in range(1_900_000, 2_100_000, 1000) if _det_workspace(3, e, nv) > cap)
+    assert _det_workspace(3, 1572864, 290353) <= cap       # the 3D elasticity workload fits
+    m = _fake_mesh(E=E, nv=nv)
+    rc = lib.fei_integrate_adjoint_det_noalloc(ctypes.byref(m), 1, None, None, FAKE, FAKE, FAKE,
+                                               FAKE, None, None, None, None)
+    assert rc == _lib.FEI_EINVAL
+    assert b"workspace" in lib.fei_last_error()
+    m = _fake_mesh(dtype=_lib.F64)                       # FP32 coordinates only
+    rc = lib.fei_integrate_adjoint_det_noalloc(ctypes.byref(m), 1, None, None, FAKE, FAKE, FAKE,
+                                               FAKE, None, None, None, None)
+    assert rc == _lib.FEI_EUNSUPPORTED
+    o = _opts(store_rows=2)                              # its own dA staging
+    rc = lib.fei_integrate_adjoint_det_noalloc(ctypes.byref(_fake_mesh()), 1, None, None, FAKE,
+                                               FAKE, FAKE, FAKE, None, None, ctypes.byref(o), None)
+    assert rc == _lib.FEI_EUNSUPPORTED
+    m = _fake_mesh(E=0)                                  # E = 0: a no-op
+    assert lib.fei_integrate_adjoint_det_noalloc(ctypes.byref(m), 1, None, None, None, None, None,
+                                                 None, None, None, None, None) == 0
