@@ -197,8 +197,8 @@ def error_summary(err):
 def adjoint_accuracy(oracle, mesh, form, g, dA, mu, lam, dmu=None, dlam=None, nverts=200,
                      nelems=2000, seed=5):
     """Vertex gradients g [N_v, dim] at sampled vertices against the oracle over all
-    their incident elements (error relative to the sum of the magnitudes of the
-    per-element terms); coefficient gradients at sampled elements, relative to
+    their incident elements (error relative to the sum of the incident elements'
+    gradient norms); coefficient gradients at sampled elements, relative to
     sum |dA| |dA/dmu| (resp. lambda)."""
     import numpy as np
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -207,9 +207,9 @@ def adjoint_accuracy(oracle, mesh, form, g, dA, mu, lam, dmu=None, dlam=None, nv
     sel = (lambda a: None if a is None else a[inc])
     gv, _, _, _ = oracle.gradient(form, mesh.coords, mesh.conn[inc], dA[inc], sel(mu), sel(lam))
     go = oracle.vertex_gradient(gv, mesh.conn[inc], mesh.n_vertices)[verts]
-    mag = np.abs(gv).max(axis=2)
+    mag = np.abs(gv).reshape(len(inc), -1).max(axis=1)      # norm of each element's gradient
     sc = np.zeros(mesh.n_vertices)
-    np.add.at(sc, mesh.conn[inc].ravel(), mag.ravel())
+    np.add.at(sc, mesh.conn[inc].ravel(), np.repeat(mag, mesh.conn.shape[1]))
     sc = sc[verts]
     ok = sc > 0
     verr = np.abs(g[verts] - go).max(axis=1)[ok] / sc[ok]
@@ -316,6 +316,135 @@ def batch_legs(fei, meshgen, oracle, dev, args, legs, copy_gbs, acc):
                                      float(max(ce)) if ce else None,
                                      "sample": "20 vertices and 50 elements per mesh"}
     b.close()
+
+
+def assembly_legs(fei, meshgen, dev, args, legs, copy_gbs, acc):
+    """Fused global assembly (the global sparse matrix, element matrices never
+    stored) of 3D P1 elasticity and the 3D P1 Laplacian on the 64^3 cube, and
+    the Laplacian with a P1 coefficient w (element matrices, eqs. 20-23)."""
+    import numpy as np
+    import torch
+    for name, make in (("assembly_elastic_p1_3d", lambda: meshgen.elast3d(args.n)),
+                       ("assembly_laplace_p1_3d", lambda: meshgen.lap3d(args.n))):
+        if not want(args, name, "assembly"):
+            continue
+        progress(f"{name}: building the plan")
+        w = make()
+        m = w.mesh
+        el = w.mu is not None
+        coords = torch.from_numpy(m.soa()).to(dev)
+        conn = torch.from_numpy(m.conn).to(dev)
+        mu = torch.from_numpy(w.mu).to(dev) if el else None
+        lam = torch.from_numpy(w.lam).to(dev) if el else None
+        asm = fei.Assembly(coords, conn, w.form)
+        nc = asm.block
+        # values (written once), conn, mu/lam, coordinates, pattern (rowptr, colidx),
+        # incidence (ptr, inc) once each
+        nbytes = (asm.nnz * nc * nc * 4 + m.conn.nbytes + (8 * m.n_elements if el else 0)
+                  + m.n_vertices * 3 * 4 + 4 * (asm.n_rows + 1) + 4 * asm.nnz
+                  + 4 * (m.n_vertices + 1) + 4 * m.conn.size)
+        # enough value arrays that the cycle exceeds twice the cache
+        S = max(2, -(-2 * MALL_BYTES // (asm.nnz * nc * nc * 4)) + 1)
+        outs = [torch.empty((asm.nnz, nc, nc), dtype=torch.float32, device=dev) for _ in range(S)]
+        fns = [(lambda k=k: asm.assemble(mu, lam, out=outs[k])) for k in range(S)]
+        r = time_leg(fns, args.steps, args.warmup, name)
+        legs[name] = rates(r, nbytes, m.n_elements, 0, copy_gbs, stored_traffic(name))
+        legs[name].update(nnz_blocks=asm.nnz, block=nc, output_sets=S,
+                          note="element matrices/s counts the elements integrated into the "
+                               "global matrix per launch")
+        if not args.no_accuracy:
+            import oracle
+            import scipy.sparse as sp
+            fns[0]()
+            rowptr, colidx = asm.pattern()
+            vals = outs[0].cpu().numpy()
+            K = sp.bsr_matrix((vals, colidx.cpu().numpy(), rowptr.cpu().numpy()),
+                              shape=(nc * asm.n_rows,) * 2).tocsr()
+            rng = np.random.Generator(np.random.PCG64(11))
+            verts = rng.choice(m.n_vertices, 200, replace=False)
+            inc = np.nonzero(np.isin(m.conn, verts).any(axis=1))[0]
+            sel = (lambda a: None if a is None else a[inc])
+            Ko = oracle.assemble(w.form, m.coords, m.conn[inc], sel(w.mu), sel(w.lam))
+            Ae = oracle.integrate(w.form, m.coords, m.conn[inc], sel(w.mu), sel(w.lam))
+            nrm = np.abs(Ae).reshape(len(inc), -1).max(axis=1)
+            dofs = (nc * m.conn[inc].astype(np.int64)[:, :, None] + np.arange(nc)).reshape(len(inc), -1)
+            nl = dofs.shape[1]
+            Sc = sp.coo_matrix((np.repeat(nrm, nl * nl), (np.repeat(dofs, nl, axis=1).ravel(),
+                                                         np.tile(dofs, (1, nl)).ravel())),
+                               shape=Ko.shape).tocsr()
+            rows = (nc * verts[:, None] + np.arange(nc)).ravel()
+            Kr, Kor, Sr = K[rows], Ko[rows], Sc[rows]
+            for X in (Kr, Kor, Sr):
+                X.sort_indices()
+            err = np.abs(Kr.data - Kor.data) / Sr.data
+            acc[name] = dict(error_summary(err), sample="200 block rows; error relative to the "
+                             "sum of the contributing element matrices' norms")
+        asm.close()
+        del outs
+        torch.cuda.empty_cache()
+    name = "coefficient_laplace_p1_3d"
+    if want(args, name, "assembly"):
+        wl = meshgen.lap3d(args.n)
+        ml = wl.mesh
+        El, Nl = ml.n_elements, ml.n_vertices
+        wv = np.exp(0.5 * np.random.Generator(np.random.PCG64(12)).standard_normal(Nl)).astype(np.float32)
+        nbytes = forward_bytes(El, Nl, 4, 3, False) + 4 * Nl
+        S = max(2, -(-2 * MALL_BYTES // nbytes) + 1)
+        sets = replicate(torch, dev, (ml.soa(), ml.conn, wv), S)
+        outs = [torch.empty((El, 4, 4), dtype=torch.float32, device=dev) for _ in range(S)]
+        fns = [(lambda k=k: fei.integrate_coefficient(sets[k][0], sets[k][1], "laplace_p1",
+                                                      sets[k][2], out=outs[k])) for k in range(S)]
+        r = time_leg(fns, args.steps, args.warmup, name)
+        legs[name] = rates(r, nbytes, El, paper_flops(3, 4) * 4, copy_gbs, stored_traffic(name))
+        legs[name]["note"] = ("A_ij = int w grad phi_i . grad phi_j, w in P1 (arity-3 K); "
+                              "paper-convention flops 2 d^2 n^2 (d + 1) per element")
+        if not args.no_accuracy:
+            import oracle
+            idx = np.sort(np.random.Generator(np.random.PCG64(13)).choice(El, 50000, replace=False))
+            fns[0]()
+            Ag = outs[0][torch.from_numpy(idx).to(dev)].cpu().numpy()
+            Ao = oracle.integrate_coefficient("laplace_p1", ml.coords, ml.conn[idx], wv)
+            acc[name] = dict(error_summary(element_errors(Ag, Ao)), sample="50,000 elements")
+        del sets, outs
+        torch.cuda.empty_cache()
+
+
+def form_leg(fei, meshgen, dev, args, legs, copy_gbs, acc, S):
+    """The headline elasticity written in the form language and integrated by
+    the front end's generic kernel (runtime Khat and recipe), beside the
+    specialized kernel of the fp32 leg."""
+    import numpy as np
+    import torch
+    from paper_1103_0066_amd import forms as F
+    name = "form_elastic_p1_3d"
+    el = F.Element(3, 1, vector=True)
+    u, v = F.TrialFunction(el), F.TestFunction(el)
+    mu, lam = F.Coefficient("mu"), F.Coefficient("lam")
+    form = F.compile_form(2 * mu * F.inner(F.eps(u), F.eps(v)) + lam * F.div(u) * F.div(v))
+    w = meshgen.elast3d(args.n)
+    m = w.mesh
+    E = m.n_elements
+    sets = replicate(torch, dev, (m.soa(), m.conn, w.mu, w.lam), S)
+    outs = [torch.empty((E, 12, 12), dtype=torch.float32, device=dev) for _ in range(S)]
+    fns = [(lambda k=k: form.integrate(sets[k][0], sets[k][1],
+                                       {"mu": sets[k][2], "lam": sets[k][3]}, out=outs[k]))
+           for k in range(S)]
+    r = time_leg(fns, args.steps, args.warmup, name)
+    nb = forward_bytes(E, m.n_vertices, 12, 3, True)
+    legs[name] = rates(r, nb, E, paper_flops(3, 12), copy_gbs, stored_traffic(name))
+    legs[name]["note"] = ("2 mu inner(eps(u), eps(v)) + lam div(u) div(v) through the form front "
+                          "end: Khat over values and reference derivatives and the G recipe at run "
+                          "time (the fp32 leg's kernel has them compiled in)")
+    if not args.no_accuracy:
+        import oracle
+        idx = np.sort(np.random.Generator(np.random.PCG64(14)).choice(E, 50000, replace=False))
+        fns[0]()
+        Ag = outs[0][torch.from_numpy(idx).to(dev)].cpu().numpy()
+        Ao = oracle.integrate("elastic_p1", m.coords, m.conn[idx], w.mu[idx], w.lam[idx])
+        acc[name] = dict(error_summary(element_errors(Ag, Ao)), sample="50,000 elements")
+    form.close()
+    del sets, outs
+    torch.cuda.empty_cache()
 
 
 def main():
@@ -598,6 +727,13 @@ def main():
             import oracle
             Ao = oracle.integrate("laplace_p1", m2.coords, m2.conn)
             acc["laplace2d_f64_latency"] = error_summary(element_errors(A2d.cpu().numpy(), Ao))
+
+    if any(want(args, k, "assembly") for k in ("assembly_elastic_p1_3d", "assembly_laplace_p1_3d",
+                                                "coefficient_laplace_p1_3d")):
+        assembly_legs(fei, meshgen, dev, args, legs, copy_gbs, acc)
+
+    if want(args, "form_elastic_p1_3d", "forms"):
+        form_leg(fei, meshgen, dev, args, legs, copy_gbs, acc, S)
 
     if want(args, "batch", "batch"):
         import oracle

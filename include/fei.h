@@ -125,8 +125,10 @@ typedef struct fei_options {
                                chunks the same way).  R must divide n with
                                R*n a multiple of 4 (the forward also takes
                                R = n for any n: 3x3 matrices are staged
-                               packed), and for the adjoint also R*n <= 48;
-                               FEI_EUNSUPPORTED otherwise. */
+                               packed), and for the adjoint also R*n <= 48
+                               or R = n (whole matrices, staged 64 or 32
+                               elements at a time); FEI_EUNSUPPORTED
+                               otherwise. */
     int32_t reserved[4];    /* must be zero */
 } fei_options;
 
@@ -368,6 +370,44 @@ int fei_assembly_copy_pattern(const fei_assembly *a, int32_t *rowptr, int32_t *c
 int fei_assemble(const fei_assembly *a, const fei_mesh *m, const float *mu, const float *lam,
                  float *values, const fei_options *opt, void *stream);
 int fei_assembly_destroy(fei_assembly *a);
+
+/* ---- form front end ---------------------------------------------------------
+ * Bilinear forms of Lagrange elements described at run time (the forms a form
+ * language describes, Sec. 3.2), integrated by the same contraction (Sec. 3,
+ * eq. 1) with a reference tensor built a priori (Sec. 3.1):
+ *
+ *   A_{(i,c),(j,d)} = int_e sum_{a,b} C[(a,c),(b,d)] D_a phi_i D_b phi_j
+ *                   = sum_{p,q} G_{(p,c),(q,d)} Khat_ij^{pq}
+ *
+ * D_0 = the value, D_{1+alpha} = d/dx_alpha; C = W_0 + sum_k coef_k(e) W_k with
+ * per-element coefficients; Khat_ij^{pq} = int_ref Dhat_p phi_i Dhat_q phi_j
+ * over values and reference derivatives (eq. 7 extended to values), computed
+ * exactly; G = |det J| That^T C That with That the map from physical to
+ * reference derivatives (J^-1, eq. 8).  DOFs node-major, I = ncomp * i + c;
+ * the P2 basis and its DOF order as in FEI_LAPLACE_P2.                     */
+typedef struct fei_weak_form fei_weak_form;
+
+/* Compiles a form: dim 2 or 3, degree 1 or 2, ncomp 1 (scalar) or dim
+ * (vector), 0 <= n_coef <= 4 per-element coefficients, and the operator
+ * tables W [n_coef + 1][m][m] (HOST, m = (dim + 1) * ncomp, index a * ncomp + c,
+ * row = the test function's operator) -- the weak-form description.  Builds
+ * Khat and uploads W and Khat (the plan owns them; FEI_ENOMEM if that fails).
+ * A form whose tables are all symmetric is integrated as symmetric.          */
+int fei_form_create(int dim, int degree, int ncomp, int n_coef, const double *W,
+                    fei_weak_form **out);
+/* Element matrix size n, whether the form is symmetric, and n_coef.          */
+int fei_form_info(const fei_weak_form *f, int32_t *n, int32_t *symmetric, int32_t *n_coef);
+/* Khat [nb][nb][dim + 1][dim + 1] of the degree-`degree` scalar Lagrange basis
+ * (double, HOST, the exact rationals rounded once); with K == NULL only *len
+ * is written.  Host-only: needs no device.                                  */
+int fei_form_reference_tensor(int dim, int degree, double *K, int64_t *len);
+/* A[e] (device [E][n][n] FP32, 16-byte aligned, overwritten) for every element
+ * of m (FP32 coordinates, m->dim == the form's dim); coef device [n_coef][E]
+ * FP32 (NULL when n_coef == 0).  opt: precision FP32, store_rows 0; tau and
+ * counters as for fei_integrate.  Asynchronous on `stream`.                 */
+int fei_form_integrate(const fei_weak_form *f, const fei_mesh *m, const float *coef, float *A,
+                       const fei_options *opt, void *stream);
+int fei_form_destroy(fei_weak_form *f);
 
 #ifdef __cplusplus
 }

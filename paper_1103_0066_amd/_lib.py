@@ -31,7 +31,8 @@ EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_d
            "fei_batch_run_adjoint", "fei_batch_tune", "fei_batch_get_config", "fei_batch_set_config",
            "fei_batch_copy_incidence", "fei_batch_destroy", "fei_assembly_create",
            "fei_assembly_info", "fei_assembly_copy_pattern", "fei_assemble",
-           "fei_assembly_destroy")
+           "fei_assembly_destroy", "fei_form_create", "fei_form_info", "fei_form_reference_tensor",
+           "fei_form_integrate", "fei_form_destroy")
 
 
 class FeiMesh(ctypes.Structure):
@@ -128,6 +129,13 @@ def load():
     lib.fei_assemble.argtypes = [vp, ctypes.POINTER(FeiMesh), f32p, f32p, f32p,
                                  ctypes.POINTER(FeiOptions), vp]
     lib.fei_assembly_destroy.argtypes = [vp]
+    lib.fei_form_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                    ctypes.POINTER(vp)]
+    lib.fei_form_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.fei_form_reference_tensor.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(i64)]
+    lib.fei_form_integrate.argtypes = [vp, ctypes.POINTER(FeiMesh), f32p, f32p,
+                                       ctypes.POINTER(FeiOptions), vp]
+    lib.fei_form_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(lib, name)
     _lib = lib

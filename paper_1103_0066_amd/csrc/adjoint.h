@@ -19,7 +19,11 @@
 //
 // dA is read through LDS: the wave loads R rows of its 64 elements' dA with
 // consecutive lanes on consecutive 16-byte pieces, then every lane folds its
-// own rows into U.
+// own rows into U.  With R = n (whole matrices) the wave stages EC of its
+// element matrices at a time (32 for the 12 x 12 and 10 x 10 matrices, 64 for
+// the smaller ones): each chunk is one contiguous, line-aligned run of dA, the
+// next chunk's loads are in flight while the lanes owning this chunk's
+// elements fold it, and no line is fetched twice.
 //
 // Elements flagged by the quality test run the reverse geometry in FP64, and
 // their U is recomputed in FP64 too: for such a tet (kappa ~ 1e3) the FP32
@@ -274,17 +278,44 @@ struct AdjTile {
     using AccT = typename std::conditional<sizeof(CT) == 8, double, float>::type;
     static constexpr int NN = S::NN;
     static constexpr int GP = ((T::G + 1) / 2) * 2;
-    static constexpr int SW = (R > 0) ? ((64 * S::STR > NN) ? 64 * S::STR : NN) : ((NN + 3) / 4) * 4;
-    // Flagged elements of a wave whose dA is kept in LDS while it streams past
-    // (further flagged elements of the same wave reload theirs from memory).
-    static constexpr int NSTASH = (R > 0 && sizeof(CT) == 4) ? 2 : 0;
-    // LDS: dA staging | FP64 fold of a flagged element | vertex-merge keys |
-    // values | stashed dA of flagged elements
+    // Whole-matrix staging (R = n, n*n a multiple of 4): EC elements per
+    // chunk, NWC chunks per wave, WP 16-byte pieces per chunk (WNP per lane).
+    static constexpr bool WHOLE = (R == T::N) && (NN % 4 == 0);
+    static constexpr int EC = WHOLE ? ((64 * (NN + 4) * 4 <= 20 * 1024) ? 64 : 32) : 64;
+    static constexpr int NWC = WHOLE ? 64 / EC : 0;
+    static constexpr int WP = EC * NN / 4;
+    static constexpr int WNP = (WP + 63) / 64;
+    // Next chunk in flight while this one is folded, where registers allow it
+    // (the 12 x 12 matrices' 18 KB chunk would hold 72 more registers next to
+    // U and the FP64 chain: the waves resident beside this one cover the
+    // latency instead).
+    static constexpr bool WPREFETCH = WNP * 4 + T::G <= 100;
     static constexpr int SLOTS = GATHER ? 0 : kHashSlots;
+    // A whole-matrix chunk buffer is reused, once the fold is done, for the
+    // FP64 fold of flagged elements (dA row + GP doubles), the vertex-merge
+    // table and the J-bar staging; it must hold each of them.
+    static constexpr int WHOLE_SW = (EC * S::STR > 64 * DIM * DIM + 4)
+        ? EC * S::STR : 64 * DIM * DIM + 4;
+    static constexpr int WHOLE_SW2 = (WHOLE_SW > SLOTS * (1 + DIM)) ? WHOLE_SW : SLOTS * (1 + DIM);
+    // (whole staging: the FP64 fold of a flagged element runs while its chunk
+    // is staged, from the chunk, into GP doubles past the chunk buffer)
+    static constexpr int WHOLE_U64 = ((WHOLE_SW2 + 1) / 2) * 2;
+    // FP64 folds of a wave's first NS64 flagged elements, kept until the
+    // reverse pass (further flagged elements reread their dA there)
+    static constexpr int NS64 = 2;
+    static constexpr int SW = WHOLE ? WHOLE_U64 + 2 * GP * (1 + NS64)
+                          : (R > 0) ? ((64 * S::STR > NN) ? 64 * S::STR : NN) : ((NN + 3) / 4) * 4;
+    // Flagged elements of a wave whose dA is kept in LDS while it streams past
+    // (further flagged elements of the same wave reload theirs from memory;
+    // with whole-matrix staging all of them do).
+    static constexpr int NSTASH = (R > 0 && !WHOLE && sizeof(CT) == 4) ? 2 : 0;
+    // LDS: dA staging | FP64 fold of a flagged element | vertex-merge keys |
+    // values | stashed dA of flagged elements (whole-matrix staging: the
+    // staging buffer alone, reused)
     static constexpr int OFF_U64 = 4 * SW * 4;
-    static constexpr int OFF_KEY = OFF_U64 + 4 * GP * 8;
-    static constexpr int OFF_VAL = OFF_KEY + 4 * SLOTS * 4;
-    static constexpr int OFF_STASH = OFF_VAL + 4 * SLOTS * DIM * 4;
+    static constexpr int OFF_KEY = OFF_U64 + (WHOLE ? 0 : 4 * GP * 8);
+    static constexpr int OFF_VAL = OFF_KEY + (WHOLE ? 0 : 4 * SLOTS * 4);
+    static constexpr int OFF_STASH = OFF_VAL + (WHOLE ? 0 : 4 * SLOTS * DIM * 4);
     static constexpr int LDS_BYTES = OFF_STASH + 4 * NSTASH * NN * 4;
 
     struct Lds {
@@ -297,6 +328,11 @@ struct AdjTile {
     __device__ static Lds lds(unsigned char *smem)
     {
         const int wave = wave_id();
+        if constexpr (WHOLE) {
+            float *b = reinterpret_cast<float *>(smem) + wave * SW;
+            return {b, reinterpret_cast<double *>(b + WHOLE_U64), reinterpret_cast<int *>(b),
+                    b + SLOTS, nullptr};
+        }
         return {reinterpret_cast<float *>(smem) + wave * SW,
                 reinterpret_cast<double *>(smem + OFF_U64) + wave * GP,
                 reinterpret_cast<int *>(smem + OFF_KEY) + wave * SLOTS,
@@ -312,7 +348,7 @@ struct AdjTile {
         float mu, lam;
     };
     struct Chunk {       // the wave's 16-byte dA pieces of one staged chunk
-        f32x4_t r[(R > 0) ? S::NV4 : 1];
+        f32x4_t r[WHOLE ? WNP : (R > 0) ? S::NV4 : 1];
     };
 
     // Loads of lanes past the last element (and of tiles past the end) read
@@ -408,6 +444,59 @@ struct AdjTile {
         wave_sync();
     }
 
+    // Whole-matrix chunk c of the wave: elements e0 + c EC .. + EC as one
+    // contiguous run, consecutive lanes on consecutive 16-byte pieces (pieces of
+    // elements past the last one read the last element).
+    __device__ static Chunk load_whole(const AdjParams &p, int64_t blk, int c)
+    {
+        Chunk ch;
+        if constexpr (WHOLE) {
+            const int lane = threadIdx.x & 63;
+            const int64_t eb = blk * 256 + wave_id() * 64 + c * EC;
+#pragma unroll
+            for (int k = 0; k < WNP; ++k) {
+                const int f = lane + 64 * k;
+                if (WP % 64 == 0 || f < WP) {
+                    const int el = f / S::NV4, part = f - el * S::NV4;
+                    ch.r[k] = *reinterpret_cast<const f32x4_t *>(
+                        p.dA + clamp(p, eb + el) * (int64_t)NN + 4 * part);
+                }
+            }
+        }
+        return ch;
+    }
+
+    __device__ static void stage_whole(const Lds &L, const Chunk &ch)
+    {
+        if constexpr (WHOLE) {
+            const int lane = threadIdx.x & 63;
+#pragma unroll
+            for (int k = 0; k < WNP; ++k) {
+                const int f = lane + 64 * k;
+                if (WP % 64 == 0 || f < WP) {
+                    const int el = f / S::NV4, part = f - el * S::NV4;
+                    *reinterpret_cast<f32x4_t *>(L.st + el * S::STR + 4 * part) = ch.r[k];
+                }
+            }
+        }
+    }
+
+    // The lanes whose elements are in staged chunk c fold them.
+    __device__ static void fold_whole(const Lds &L, int c, AccT (&U)[T::G])
+    {
+        if constexpr (WHOLE) {
+            const int lane = threadIdx.x & 63;
+            if (lane / EC != c) return;
+            const float *row = L.st + (lane % EC) * S::STR;
+#pragma unroll
+            for (int k = 0; k < NN; k += 4) {
+                const f32x4_t w = *reinterpret_cast<const f32x4_t *>(row + k);
+                const float r[4] = {w[0], w[1], w[2], w[3]};
+                fold_piece<FORM, DIM, AccT>(U, k, r, 4);
+            }
+        }
+    }
+
     // R == 0: every lane folds its own dA directly (plain loads: the lines a
     // lane touches are completed by its neighbours' reads through L2).
     __device__ static void fold_direct(const AdjParams &p, int64_t blk, AccT (&U)[T::G])
@@ -429,6 +518,44 @@ struct AdjTile {
         float mubar, lambar;
         bool flag, singular;
     };
+
+    // FP64 fold of one element whose dA (NN floats) is at src in LDS: the wave
+    // folds U into u64 (one lane per unique entry g, sparse rows of K').
+    __device__ static void fold_fp64(const float *src, double *u64)
+    {
+        const int lane = threadIdx.x & 63;
+        if (lane < T::G) {
+            constexpr int NZ = KSparseShape<FORM, DIM>::NNZ;
+            const KSparse<FORM, DIM> &ks = g_ksparse<FORM, DIM>;
+            double u = 0.0;
+            for (int t = 0; t < NZ; ++t) u += double(ks.coef[lane][t]) * double(src[ks.ij[lane][t]]);
+            u64[lane] = u;
+        }
+        wave_sync();
+    }
+
+    // FP64 chain of lane Lf's element from its FP64 fold u64.
+    __device__ static void chain_fp64(int Lf, const Xv &g, const double *u64, Rev &o)
+    {
+        if ((threadIdx.x & 63) == Lf) {
+            double Jd[DIM][DIM], adjd[DIM][DIM];
+            jacobian<DIM>(g.x, Jd);
+            const double detd = adjugate(Jd, adjd);
+            o.singular = (detd == 0.0);
+            adjoint_chain<FORM, DIM>(adjd, detd, g.mu, g.lam, SLds{u64, T::GD}, o.Jbar,
+                                     o.mubar, o.lambar);
+        }
+        wave_sync();
+    }
+
+    // Flagged element of lane Lf whose dA (NN floats) is at src in LDS: the
+    // wave folds U in FP64, then the owner runs the FP64 chain.
+    __device__ static void flagged_fp64(const float *src, int Lf, const Xv &g, const Lds &L,
+                                        Rev &o)
+    {
+        fold_fp64(src, L.u64);
+        chain_fp64(Lf, g, L.u64, o);
+    }
 
     // Reverse geometry of a tile whose U is folded.  fm: the wave's flagged
     // lanes, the first NSTASH of them with their dA in the stash.
@@ -461,7 +588,7 @@ struct AdjTile {
             while (fm) {
                 const int Lf = __ffsll(fm) - 1;
                 fm &= fm - 1;
-                const float *src = L.stash + slot * NN;
+                const float *src = NSTASH > 0 ? L.stash + slot * NN : L.st;
                 if (slot >= NSTASH) {
                     for (int k = lane; k < NN; k += 64)
                         L.st[k] = __builtin_nontemporal_load(p.dA + (e0 + Lf) * (int64_t)NN + k);
@@ -469,24 +596,7 @@ struct AdjTile {
                 }
                 ++slot;
                 wave_sync();
-                if (lane < T::G) {
-                    constexpr int NZ = KSparseShape<FORM, DIM>::NNZ;
-                    const KSparse<FORM, DIM> &ks = g_ksparse<FORM, DIM>;
-                    double u = 0.0;
-                    for (int t = 0; t < NZ; ++t)
-                        u += double(ks.coef[lane][t]) * double(src[ks.ij[lane][t]]);
-                    L.u64[lane] = u;
-                }
-                wave_sync();
-                if (lane == Lf) {
-                    double Jd[DIM][DIM], adjd[DIM][DIM];
-                    jacobian<DIM>(g.x, Jd);
-                    const double detd = adjugate(Jd, adjd);
-                    o.singular = (detd == 0.0);
-                    adjoint_chain<FORM, DIM>(adjd, detd, g.mu, g.lam, SLds{L.u64, T::GD}, o.Jbar,
-                                             o.mubar, o.lambar);
-                }
-                wave_sync();
+                flagged_fp64(src, Lf, g, L, o);
             }
         }
         return o;
@@ -538,25 +648,89 @@ struct AdjTile {
     __device__ __forceinline__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem)
     {
         const Lds L = lds(smem);
-        const In in = load(p, blk);
-        Chunk ch = load_chunk(p, blk, 0);
-        const Xv g = gather_xv(p, blk, in);
-        const unsigned long long fm = __ballot(flagged(p, blk, g));
-        AccT U[T::G];
+        if constexpr (WHOLE) {
+            // coordinates first (their loads complete before dA's), then the
+            // chunks: chunk c + 1 is in flight while chunk c is folded
+            // Flagged elements: the FP64 fold of the wave's first NS64 of them
+            // runs while their chunk is staged (no second read of their dA) and
+            // is kept in LDS; the FP64 chains run after the FP32 ones, once U
+            // is no longer live.
+            const In in = load(p, blk);
+            const Xv g = gather_xv(p, blk, in);
+            Chunk ch = load_whole(p, blk, 0);
+            const unsigned long long fm = __ballot(flagged(p, blk, g));
+            const int lane = threadIdx.x & 63;
+            Rev o;
+            o.mubar = o.lambar = 0.f;
+            o.singular = false;
+            o.flag = (fm >> lane) & 1;
+            AccT U[T::G];
 #pragma unroll
-        for (int k = 0; k < T::G; ++k) U[k] = AccT(0);
-        if constexpr (R > 0) {
+            for (int k = 0; k < T::G; ++k) U[k] = AccT(0);
 #pragma unroll
-            for (int c = 0; c < S::NCHUNK; ++c) {
-                Chunk nx;
-                if (c + 1 < S::NCHUNK) nx = load_chunk(p, blk, c + 1);
-                fold_chunk(L, c, ch, fm, U);
-                if (c + 1 < S::NCHUNK) ch = nx;
+            for (int c = 0; c < NWC; ++c) {
+                if (!WPREFETCH && c > 0) ch = load_whole(p, blk, c);
+                stage_whole(L, ch);
+                if (WPREFETCH && c + 1 < NWC) ch = load_whole(p, blk, c + 1);
+                wave_sync();
+                fold_whole(L, c, U);
+                // flagged elements of this chunk among the wave's first NS64
+                unsigned long long fc = fm;
+                for (int sl = 0; sl < NS64 && fc; ++sl) {
+                    const int Lf = __ffsll(fc) - 1;
+                    fc &= fc - 1;
+                    if (Lf / EC == c) fold_fp64(L.st + (Lf % EC) * S::STR, L.u64 + GP * (1 + sl));
+                }
+                wave_sync();
             }
+            if constexpr (sizeof(CT) == 8) {
+                o = reverse(p, blk, g, U, 0ull, L);
+            } else {
+                if (!o.flag) {
+                    float J[DIM][DIM], adj[DIM][DIM];
+                    jacobian<DIM>(g.x, J);
+                    const float det = adjugate(J, adj);
+                    adjoint_chain<FORM, DIM>(adj, det, g.mu, g.lam, SRegs<FORM, DIM, AccT>{U},
+                                             o.Jbar, o.mubar, o.lambar);
+                }
+                const int64_t e0 = blk * 256 + wave_id() * 64;
+                unsigned long long fc = fm;
+                for (int sl = 0; fc; ++sl) {
+                    const int Lf = __ffsll(fc) - 1;
+                    fc &= fc - 1;
+                    if (sl < NS64) {
+                        chain_fp64(Lf, g, L.u64 + GP * (1 + sl), o);
+                    } else {
+                        // dA reread from memory into the (free) chunk buffer
+                        for (int k = lane; k < NN; k += 64)
+                            L.st[k] = __builtin_nontemporal_load(p.dA + (e0 + Lf) * (int64_t)NN + k);
+                        wave_sync();
+                        flagged_fp64(L.st, Lf, g, L, o);
+                    }
+                }
+            }
+            emit(p, blk, in, o, L);
         } else {
-            fold_direct(p, blk, U);
+            const In in = load(p, blk);
+            Chunk ch = load_chunk(p, blk, 0);
+            const Xv g = gather_xv(p, blk, in);
+            const unsigned long long fm = __ballot(flagged(p, blk, g));
+            AccT U[T::G];
+#pragma unroll
+            for (int k = 0; k < T::G; ++k) U[k] = AccT(0);
+            if constexpr (R > 0) {
+#pragma unroll
+                for (int c = 0; c < S::NCHUNK; ++c) {
+                    Chunk nx;
+                    if (c + 1 < S::NCHUNK) nx = load_chunk(p, blk, c + 1);
+                    fold_chunk(L, c, ch, fm, U);
+                    if (c + 1 < S::NCHUNK) ch = nx;
+                }
+            } else {
+                fold_direct(p, blk, U);
+            }
+            emit(p, blk, in, reverse(p, blk, g, U, fm, L), L);
         }
-        emit(p, blk, in, reverse(p, blk, g, U, fm, L), L);
     }
 };
 
@@ -576,7 +750,7 @@ __global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p, int64_t n_til
     using AccT = typename Tile::AccT;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
     const PersistentTiles pt(n_tiles);
-    if constexpr (R == 0) {
+    if constexpr (R == 0 || Tile::WHOLE) {
         for (int64_t t = pt.begin; t < pt.end; t += pt.stride) Tile::run(p, t, smem);
     } else {
         constexpr int NCH = Stage<FORM, DIM, R>::NCHUNK;

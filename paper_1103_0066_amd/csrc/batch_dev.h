@@ -31,7 +31,7 @@ constexpr int batch_adj_rows()
 {
     constexpr int N = Traits<F, D>::N;
     if constexpr (N == 3) return 0;
-    else if constexpr (VAR == 0) return (N == 12) ? 4 : (N == 10) ? 2 : N;
+    else if constexpr (VAR == 0) return (N == 12) ? 4 : N;
     else return 2;
 }
 

@@ -10,6 +10,7 @@
 #include "batch_dev.h"
 #include "gather.h"
 #include "fwd_coef.h"
+#include "fwd_form.h"
 #include "fwd_fma.h"
 #include "fwd_mfma.h"
 
@@ -78,10 +79,10 @@ hipError_t launch_fwd_mfma(const FwdParams &p, hipStream_t s)
 template <int F, int D, typename CT, int R, bool GATHER = false>
 hipError_t launch_adj_fma(const AdjParams &p, hipStream_t s)
 {
-    if constexpr (GATHER) {
+    if constexpr (GATHER || AdjTile<F, D, CT, R, false>::WHOLE) {
         const int64_t n_tiles = (p.m.n_elements + kBlock - 1) / kBlock;
         if (n_tiles == 0) return hipSuccess;
-        hipLaunchKernelGGL((adj_tile_kernel<F, D, CT, R, true>), dim3(unsigned(n_tiles)),
+        hipLaunchKernelGGL((adj_tile_kernel<F, D, CT, R, GATHER>), dim3(unsigned(n_tiles)),
                            dim3(kBlock), 0, s, p);
         return hipGetLastError();
     } else {
@@ -118,22 +119,30 @@ constexpr int default_rows()
     return Traits<F, D>::N;
 }
 
+// Adjoint staging defaults (measured on MI355X).  Whole matrices (R = n,
+// staged 64 or 32 elements at a time, line-aligned) for the 4 x 4 and
+// 10 x 10 matrices: 3D P1 Laplacian 144 -> 132 us, 3D P2 Laplacian 204 ->
+// 178 us (direct per-lane reads before).  The 12 x 12 elasticity matrices
+// keep 2-row chunks in the persistent, software-pipelined kernel: whole
+// 32-matrix chunks leave no registers for an in-flight chunk next to the
+// 45 folded sums and measured 388 against 265 us.
 template <int F, int D>
 constexpr int default_adj_rows()
 {
     constexpr int N = Traits<F, D>::N;
-    if constexpr (N == 4) return 4;
+    if constexpr (N == 4 || N == 10) return N;
     else if constexpr (N == 12 || N == 6) return 2;
-    else return 0;     // 10 x 10: direct per-lane reads (197 vs 208 us at R = 2)
+    else return 0;
 }
 
-// The gather form (no vertex table, one workgroup per tile) is fastest with
-// larger chunks for 3D elasticity (measured R = 4 against R = 2 and 3).
+// The gather form (no vertex table, one workgroup per tile): R = 4 for 3D
+// elasticity (measured against R = 2, 3 and whole matrices: 260 vs 395 us),
+// whole matrices for the 10 x 10 ones (183 vs 206 us at R = 2).
 template <int F, int D>
 constexpr int default_gather_rows()
 {
     constexpr int N = Traits<F, D>::N;
-    return N == 12 ? 4 : (N == 10 ? 2 : default_adj_rows<F, D>());
+    return N == 12 ? 4 : default_adj_rows<F, D>();
 }
 
 template <int F, int D, typename CT, int R>
@@ -150,7 +159,7 @@ FwdLauncher fwd_fma_if_ok()
 template <int F, int D, typename CT, int R>
 AdjLauncher adj_fma_if_ok()
 {
-    if constexpr (rows_ok<F, D, R>() && R * Traits<F, D>::N <= 48)
+    if constexpr (rows_ok<F, D, R>() && (R * Traits<F, D>::N <= 48 || R == Traits<F, D>::N))
         return &launch_adj_fma<F, D, CT, R>;
     else return nullptr;
 }
@@ -181,6 +190,8 @@ AdjLauncher adj_fma_rows(int rows)
     case 3: return adj_fma_if_ok<F, D, CT, 3>();
     case 4: return adj_fma_if_ok<F, D, CT, 4>();
     case 6: return adj_fma_if_ok<F, D, CT, 6>();
+    case 10: return adj_fma_if_ok<F, D, CT, 10>();
+    case 12: return adj_fma_if_ok<F, D, CT, 12>();
     default: return nullptr;
     }
 }
@@ -499,6 +510,41 @@ hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad
     const unsigned grid = unsigned(want < 4096 ? (want > 0 ? want : 1) : 4096);
     hipLaunchKernelGGL(validate_kernel, dim3(grid), dim3(kBlock), 0, s, m, dim + 1, n_bad_dev);
     return hipGetLastError();
+}
+
+template <int D, int DEG, int NC, bool SYM, bool NOVAL>
+hipError_t launch_form_t(const FormParams &p, hipStream_t s)
+{
+    const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
+    if (n_groups == 0) return hipSuccess;
+    hipLaunchKernelGGL((form_kernel<D, DEG, NC, SYM, NOVAL>), dim3(unsigned(n_groups)), dim3(kBlock),
+                       0, s, p);
+    return hipGetLastError();
+}
+
+template <int D, int DEG, int NC>
+hipError_t launch_form_sym(bool sym, bool noval, const FormParams &p, hipStream_t s)
+{
+    if (noval)
+        return sym ? launch_form_t<D, DEG, NC, true, true>(p, s)
+                   : launch_form_t<D, DEG, NC, false, true>(p, s);
+    return sym ? launch_form_t<D, DEG, NC, true, false>(p, s)
+               : launch_form_t<D, DEG, NC, false, false>(p, s);
+}
+
+hipError_t launch_form(int dim, int degree, int ncomp, bool sym, bool noval, const FormParams &p,
+                       hipStream_t s)
+{
+    const bool vec = ncomp == dim;
+    if (ncomp != 1 && !vec) return hipErrorInvalidValue;
+    if (dim == 2) {
+        if (degree == 1) return vec ? launch_form_sym<2, 1, 2>(sym, noval, p, s) : launch_form_sym<2, 1, 1>(sym, noval, p, s);
+        if (degree == 2) return vec ? launch_form_sym<2, 2, 2>(sym, noval, p, s) : launch_form_sym<2, 2, 1>(sym, noval, p, s);
+    } else if (dim == 3) {
+        if (degree == 1) return vec ? launch_form_sym<3, 1, 3>(sym, noval, p, s) : launch_form_sym<3, 1, 1>(sym, noval, p, s);
+        if (degree == 2) return vec ? launch_form_sym<3, 2, 3>(sym, noval, p, s) : launch_form_sym<3, 2, 1>(sym, noval, p, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fei

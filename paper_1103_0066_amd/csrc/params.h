@@ -135,6 +135,26 @@ hipError_t launch_vertex_gather_one(const GatherItem &it, hipStream_t s);
 hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad_dev,
                            hipStream_t s);
 
+// Runtime-described bilinear forms (form front end): the geometric tensor
+// G = |J| That^T C_e That from the operator tables W and per-element
+// coefficients, contracted with the reference tensor Khat.
+constexpr int kFormMaxCoef = 4;
+struct FormParams {
+    MeshView m;
+    const float *coef;         // [n_coef][E] per-element coefficients, or NULL
+    int32_t n_coef;            // 0 .. kFormMaxCoef
+    const float *W;            // [n_coef + 1][M][M], M = (dim + 1) * ncomp (uniform)
+    const float *K;            // [NB][NB][dim + 1][dim + 1] (uniform), scaled by 1 / kscale
+    float kscale;              // Khat = K * kscale (folded into |det J|)
+    float *A;                  // [E][n][n]
+    int32_t *counters;
+    float tau2;
+};
+// Launches the form kernel of (dim, degree, ncomp, symmetric, no value term);
+// hipErrorInvalidValue if none exists.
+hipError_t launch_form(int dim, int degree, int ncomp, bool sym, bool noval, const FormParams &p,
+                       hipStream_t s);
+
 // Fused global assembly (P1 forms): rows of the global matrix gathered by
 // waves, one host-built chunk of rows per wave.
 struct AsmParams {

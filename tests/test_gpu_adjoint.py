@@ -88,8 +88,8 @@ def test_adjoint_matches_oracle(case):
     _check_against_oracle(mesh, form, mu, lam, dA)
 
 
-@pytest.mark.parametrize("case,rows", [("elast3d", r) for r in (-1, 2, 3, 4)] +
-                         [("lap3d", r) for r in (-1, 2, 4)] + [("p2_3d", r) for r in (-1, 2)] +
+@pytest.mark.parametrize("case,rows", [("elast3d", r) for r in (-1, 2, 3, 4, 12)] +
+                         [("lap3d", r) for r in (-1, 2, 4)] + [("p2_3d", r) for r in (-1, 2, 10)] +
                          [("elast2d", r) for r in (-1, 2, 6)])
 def test_adjoint_staging_modes(case, rows):
     mesh, form, mu, lam = _case(case)
@@ -127,7 +127,37 @@ def test_adjoint_staging_beyond_register_budget_is_rejected():
     assert ex.value.status == fei._lib.FEI_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("rows", [0, -1, 2])
+@pytest.mark.parametrize("form,rows", [("elastic_p1", 12), ("laplace_p2", 0), ("laplace_p1", 0)])
+def test_adjoint_whole_staging_with_many_flagged_elements(form, rows):
+    """Whole-matrix staging folds the first two flagged elements of a wave in
+    FP64 while their chunk is staged and rereads the dA of further ones: a
+    mesh with a third of its elements flattened (many per wave) against the
+    oracle, and the FP64-path counter."""
+    m = meshgen.cube_mesh(6, 5, 4, 0.15, 71)
+    m = meshgen.flatten_elements(m, m.n_elements // 3, 72)
+    mu = lam = None
+    if form == "elastic_p1":
+        mu, lam = meshgen.lame(m.n_elements, 73)
+    n = fei.local_size(form, 3)
+    dA = meshgen.upstream(m.n_elements, n, 74)
+    coords, conn = mesh_to_device(m)
+    cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+    dc, dmu, dlam = fei.integrate_adjoint(coords, conn, form, vec_to_device(dA), vec_to_device(mu),
+                                          vec_to_device(lam), store_rows=rows, counters=cnt,
+                                          **_nan_coeff_buffers(m, form))
+    g = dc.cpu().numpy().T.astype(np.float64)
+    gv, gm, gl, _ = oracle.gradient(form, m.coords, m.conn, dA, mu, lam)
+    go = oracle.vertex_gradient(gv, m.conn, m.n_vertices)
+    scale = vertex_scale(gv, m.conn, m.n_vertices)
+    used = scale > 0
+    assert (np.abs(g - go).max(axis=1)[used] / scale[used]).max() <= TOL_VERTEX
+    if dmu is not None:
+        assert _coeff_errors(m.coords, m.conn, dA, dmu.cpu().numpy(), dlam.cpu().numpy(),
+                             gm, gl).max() <= TOL_COEFF
+    assert cnt.cpu().tolist() == [len(m.flattened), 0]
+
+
+@pytest.mark.parametrize("rows", [0, -1, 2, 12])
 def test_adjoint_every_tile_count_is_covered(rows):
     """1 to 11 workgroup tiles (the persistent adjoint splits tiles over the XCDs
     that have workgroups): every element and vertex contribution counted once."""
