@@ -214,6 +214,70 @@ def upstream(E: int, n: int, seed: int) -> np.ndarray:
     return rng.standard_normal(size=(E, n, n), dtype=np.float32)
 
 
+def p2_mesh(mesh: Mesh, amp: float = 0.0, wavelength: float = 1.0) -> Mesh:
+    """Quadratic (P2) geometry on a simplicial mesh: every edge gets one node,
+    shared by the elements around it, at its midpoint moved by the smooth field
+    amp * l * f(x), f = (sin(2 pi y/L) sin(2 pi z/L), sin(2 pi z/L) sin(2 pi x/L),
+    sin(2 pi x/L) sin(2 pi y/L)) in 3D and (sin(2 pi y/L), sin(2 pi x/L)) in 2D,
+    l the edge's length (amp = 0: straight edges, the affine element).
+    The returned conn is [E, nb]: the element's vertices, then its edge nodes in
+    the P2 order (0,1), (0,2), .., (d-1,d); coordinates are FP64 before
+    rounding to the mesh dtype.  Asserts det J > 0 at the vertices, the
+    barycenter and the edge midpoints of every element."""
+    dim = mesh.dim
+    nv = dim + 1
+    pairs = [(a, b) for a in range(nv) for b in range(a + 1, nv)]
+    c = mesh.conn.astype(np.int64)
+    E = c.shape[0]
+    ev = np.stack([np.sort(np.stack([c[:, a], c[:, b]], axis=1), axis=1) for a, b in pairs], axis=1)
+    key = ev[..., 0] * mesh.n_vertices + ev[..., 1]
+    uniq, inv = np.unique(key.ravel(), return_inverse=True)
+    X = mesh.coords.astype(np.float64)
+    a, b = uniq // mesh.n_vertices, uniq % mesh.n_vertices
+    mid = 0.5 * (X[a] + X[b])
+    h = np.linalg.norm(X[a] - X[b], axis=1)[:, None]
+    w = 2.0 * np.pi / wavelength
+    if dim == 3:
+        f = np.stack([np.sin(w * mid[:, 1]) * np.sin(w * mid[:, 2]),
+                      np.sin(w * mid[:, 2]) * np.sin(w * mid[:, 0]),
+                      np.sin(w * mid[:, 0]) * np.sin(w * mid[:, 1])], axis=1)
+    else:
+        f = np.stack([np.sin(w * mid[:, 1]), np.sin(w * mid[:, 0])], axis=1)
+    nodes = mid + amp * h * f
+    coords = np.concatenate([X, nodes]).astype(mesh.coords.dtype)
+    conn = np.concatenate([c, mesh.n_vertices + inv.reshape(E, len(pairs))], axis=1).astype(np.int32)
+    _assert_positive_p2(coords, conn)
+    return Mesh(coords, conn)
+
+
+def _assert_positive_p2(coords: np.ndarray, conn: np.ndarray):
+    """det J(xi) > 0 for the quadratic map at the vertices, the barycenter and
+    the edge midpoints of every element (FP64)."""
+    dim = coords.shape[1]
+    nv = dim + 1
+    X = coords.astype(np.float64)[conn]                     # [E, nb, dim]
+    gl = np.vstack([-np.ones(dim), np.eye(dim)])            # reference grad lambda_a
+    pairs = [(a, b) for a in range(nv) for b in range(a + 1, nv)]
+    pts = [np.eye(nv)[k] for k in range(nv)] + [np.full(nv, 1.0 / nv)]
+    pts += [0.5 * (np.eye(nv)[a] + np.eye(nv)[b]) for a, b in pairs]
+    for bc in pts:
+        g = [(4 * bc[k] - 1) * gl[k] for k in range(nv)]
+        g += [4 * (bc[a] * gl[b] + bc[b] * gl[a]) for a, b in pairs]
+        J = np.einsum("enx,nm->exm", X, np.array(g))
+        det = np.linalg.det(J)
+        if det.size and not (det > 0).all():
+            raise AssertionError(f"{int((det <= 0).sum())} curved elements are inverted")
+
+
+def iso3d(n: int = 64, amp: float = 0.1) -> "Workload":
+    """Isoparametric P2 Laplacian: the lap3d mesh (jittered Kuhn cube, 6 n^3
+    tets) with quadratic geometry, edge nodes moved by up to amp times the
+    edge length (curved edges)."""
+    m = p2_mesh(_cube(n), amp)
+    return Workload(f"3D isoparametric P2 Laplacian, {n}^3 Kuhn cube, {m.n_elements} curved tets, "
+                    f"{m.n_vertices} nodes, FP32", "laplace_iso_p2", m)
+
+
 # ----------------------------------------------------------------------------
 # Named workloads
 # ----------------------------------------------------------------------------

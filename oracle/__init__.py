@@ -71,6 +71,9 @@ def _load():
                                              ctypes.c_int64, dp, dp, dp, ctypes.c_int64, ip,
                                              ctypes.c_int, dp, dp, ctypes.c_int, dp]
     lib.oracle_integrate_general.restype = ctypes.c_int
+    lib.oracle_integrate_iso.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp, ctypes.c_int64,
+                                         ip, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_integrate_iso.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -197,6 +200,28 @@ def integrate_general(degree: int, ncomp: int, W, coords, conn, coefs=(), qs: in
                                       qs, _ptr(A))
     if rc:
         raise ValueError(f"oracle_integrate_general failed ({rc})")
+    return A
+
+
+def integrate_iso(coords, conn, mode: str = "projected", qs: int = 2) -> np.ndarray:
+    """Element matrices [E, nb, nb] (float64) of the isoparametric P2 Laplacian on
+    elements with quadratic geometry (Sec. 3.1, eqs. 16-19); conn [E, nb] lists
+    each element's nodes, vertices then edge nodes (the P2 order).
+    mode "projected": the paper's scheme -- J^-1 interpolated linearly from its
+    values at the vertices, |J| the constant |det J| at the barycenter;
+    mode "exact": the isoparametric integral with J(xi) at every point."""
+    lib = _load()
+    dim, x, y, z = _coords_soa(coords)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    E, nb = conn.shape
+    if nb != (dim + 1) * (dim + 2) // 2:
+        raise ValueError("conn must list the P2 nodes of each element")
+    A = np.empty((E, nb, nb))
+    rc = lib.oracle_integrate_iso(dim, x.shape[0], _ptr(x), _ptr(y), _ptr(z), E,
+                                  _ptr(conn, ctypes.c_int32), {"projected": 0, "exact": 1}[mode],
+                                  qs, _ptr(A))
+    if rc:
+        raise ValueError(f"oracle_integrate_iso failed ({rc})")
     return A
 
 

@@ -287,6 +287,137 @@ int oracle_integrate_general(int degree, int dim, int ncomp, int64_t nv,
     return bad ? -2 : 0;
 }
 
+/* ---- isoparametric P2 Laplacian (Sec. 3.1, eqs. 16-19) ------------------ */
+
+/* Reference gradients d psi_n / d xi_mu of the P2 basis (vertices, then edges
+ * (0,1),(0,2),..) at the barycentric point bc; lambda_0 = 1 - sum xi,
+ * lambda_{m+1} = xi_m.                                                      */
+static void p2_ref_gradients(int dim, const double *bc, double g[10][3])
+{
+    const int nv = dim + 1;
+    double gl[4][3];
+    for (int a = 0; a < nv; ++a)
+        for (int mu = 0; mu < dim; ++mu) gl[a][mu] = (a == 0) ? -1.0 : (a - 1 == mu ? 1.0 : 0.0);
+    for (int a = 0; a < nv; ++a)
+        for (int mu = 0; mu < dim; ++mu) g[a][mu] = (4.0 * bc[a] - 1.0) * gl[a][mu];
+    int e = nv;
+    for (int a = 0; a < nv; ++a)
+        for (int b = a + 1; b < nv; ++b, ++e)
+            for (int mu = 0; mu < dim; ++mu) g[e][mu] = 4.0 * (bc[a] * gl[b][mu] + bc[b] * gl[a][mu]);
+}
+
+/* J[alpha][mu] = sum_n x_n[alpha] dpsi_n/dxi_mu at bc; B = J^-1 (rows mu,
+ * columns alpha) by cofactors; returns det J.                              */
+static double iso_jacobian(int dim, int nb, const double xn[10][3], const double *bc,
+                           double B[3][3])
+{
+    double g[10][3], J[3][3];
+    p2_ref_gradients(dim, bc, g);
+    for (int al = 0; al < dim; ++al)
+        for (int mu = 0; mu < dim; ++mu) {
+            double s = 0.0;
+            for (int n = 0; n < nb; ++n) s += xn[n][al] * g[n][mu];
+            J[al][mu] = s;
+        }
+    double det;
+    if (dim == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        B[0][0] = J[1][1] / det;  B[0][1] = -J[0][1] / det;
+        B[1][0] = -J[1][0] / det; B[1][1] = J[0][0] / det;
+    } else {
+        double c[3][3];
+        c[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        c[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        c[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        c[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        c[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        c[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        c[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        c[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        c[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        det = J[0][0] * c[0][0] + J[0][1] * c[1][0] + J[0][2] * c[2][0];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) B[i][j] = c[i][j] / det;
+    }
+    return det;
+}
+
+/* Isoparametric P2 Laplacian on elements with quadratic geometry: conn
+ * [ne][nb] lists each element's nodes (vertices, then edge nodes in the P2
+ * order), which carry both the geometry map x(xi) = sum_n x_n psi_n(xi) and
+ * the solution basis phi_i = psi_i.
+ *   mode 0, the paper's scheme: the inverse Jacobian projected onto P1 by its
+ *     values at the vertices, J^-1(xi) ~ sum_k lambda_k(xi) J(xi_k)^-1, and
+ *     |J| taken out of the integral as a constant, |det J| at the barycenter:
+ *       A_ij = |J_c| int_ref (Bp^T dphi_i) . (Bp^T dphi_j) dxi,
+ *     an integrand of degree 4 (GM degree 2qs+1 >= 5 integrates it exactly);
+ *   mode 1, the isoparametric integral itself, J(xi) at every point:
+ *       A_ij = int_ref (J^-T dphi_i) . (J^-T dphi_j) |det J(xi)| dxi
+ *     (a rational integrand: the rule's degree sets its accuracy).        */
+int oracle_integrate_iso(int dim, int64_t nv, const double *x, const double *y,
+                         const double *z, int64_t ne, const int32_t *conn, int mode, int qs,
+                         double *A)
+{
+    if ((dim != 2 && dim != 3) || (mode != 0 && mode != 1) || qs < 0 || qs > 4) return -1;
+    const int nvert = dim + 1, nb = nvert * (nvert + 1) / 2;
+    const double *X[3] = {x, y, z};
+    double pts[ORACLE_MAX_QP][4], w[ORACLE_MAX_QP];
+    const int nq = oracle_gm_rule(dim, qs, pts, w);
+    if (nq < 0) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|:bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double xn[10][3];
+        for (int n = 0; n < nb; ++n) {
+            int32_t v = conn[e * nb + n];
+            if (v < 0 || v >= nv) { bad = 1; v = 0; }
+            for (int al = 0; al < dim; ++al) xn[n][al] = X[al][v];
+        }
+        double Bk[4][3][3], sc = 0.0;
+        if (mode == 0) {
+            for (int k = 0; k < nvert; ++k) {
+                double bc[4] = {0.0, 0.0, 0.0, 0.0};
+                bc[k] = 1.0;
+                iso_jacobian(dim, nb, xn, bc, Bk[k]);
+            }
+            double bc[4], Bc[3][3];
+            for (int a = 0; a < nvert; ++a) bc[a] = 1.0 / nvert;
+            sc = fabs(iso_jacobian(dim, nb, xn, bc, Bc));
+        }
+        double *Ae = A + e * (int64_t)nb * nb;
+        for (int t = 0; t < nb * nb; ++t) Ae[t] = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            double B[3][3], wq;
+            if (mode == 0) {
+                for (int mu = 0; mu < dim; ++mu)
+                    for (int al = 0; al < dim; ++al) {
+                        double s = 0.0;
+                        for (int k = 0; k < nvert; ++k) s += pts[q][k] * Bk[k][mu][al];
+                        B[mu][al] = s;
+                    }
+                wq = w[q] * sc;
+            } else {
+                wq = w[q] * fabs(iso_jacobian(dim, nb, xn, pts[q], B));
+            }
+            double g[10][3], gx[10][3];
+            p2_ref_gradients(dim, pts[q], g);
+            for (int i = 0; i < nb; ++i)
+                for (int al = 0; al < dim; ++al) {
+                    double s = 0.0;
+                    for (int mu = 0; mu < dim; ++mu) s += B[mu][al] * g[i][mu];
+                    gx[i][al] = s;
+                }
+            for (int i = 0; i < nb; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    double s = 0.0;
+                    for (int al = 0; al < dim; ++al) s += gx[i][al] * gx[j][al];
+                    Ae[i * nb + j] += wq * s;
+                }
+        }
+    }
+    return bad ? -2 : 0;
+}
+
 /* Complex-step gradient of L_e = sum_IJ dA_e[I][J] A_e[I][J] for each element.
  *   gvert: [ne][dim+1][dim]  dL_e / d x_{conn[e][a]}[alpha]
  *   gmu, glam: [ne] or NULL  dL_e / d mu_e, dL_e / d lambda_e
