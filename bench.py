@@ -409,6 +409,37 @@ def assembly_legs(fei, meshgen, dev, args, legs, copy_gbs, acc):
         torch.cuda.empty_cache()
 
 
+def iso_leg(fei, meshgen, dev, args, legs, copy_gbs, acc):
+    """The isoparametric P2 Laplacian (Sec. 3.1, eqs. 16-19) on the 64^3 Kuhn
+    cube with curved (quadratic) edges: 10 nodes and a 10 x 10 matrix per tet."""
+    import numpy as np
+    import torch
+    name = "iso_p2_3d"
+    progress(f"{name}: generating the curved mesh")
+    w = meshgen.iso3d(args.n)
+    m = w.mesh
+    E = m.n_elements
+    nbytes = E * (m.conn.shape[1] * 4 + 400) + m.n_vertices * 12
+    S = max(2, -(-2 * MALL_BYTES // nbytes) + 1)
+    sets = replicate(torch, dev, (m.soa(), m.conn), S)
+    outs = [torch.empty((E, 10, 10), dtype=torch.float32, device=dev) for _ in range(S)]
+    fns = [(lambda k=k: fei.integrate_iso(sets[k][0], sets[k][1], out=outs[k])) for k in range(S)]
+    r = time_leg(fns, args.steps, args.warmup, name)
+    # the dense contraction of eq. 19: (d+1)^2 d^2 terms for each of the n^2 entries
+    legs[name] = rates(r, nbytes, E, 2 * 16 * 9 * 100, copy_gbs, stored_traffic(name))
+    legs[name].update(nodes=m.n_vertices, note=(
+        "paper-convention flops: 2 (d+1)^2 d^2 n^2 per element (eq. 19's contraction)"))
+    if not args.no_accuracy:
+        import oracle
+        idx = np.sort(np.random.Generator(np.random.PCG64(15)).choice(E, 50000, replace=False))
+        fns[0]()
+        Ag = outs[0][torch.from_numpy(idx).to(dev)].cpu().numpy()
+        Ao = oracle.integrate_iso(m.coords, m.conn[idx])
+        acc[name] = dict(error_summary(element_errors(Ag, Ao)), sample="50,000 elements")
+    del sets, outs
+    torch.cuda.empty_cache()
+
+
 def form_leg(fei, meshgen, dev, args, legs, copy_gbs, acc, S):
     """The headline elasticity written in the form language and integrated by
     the front end's generic kernel (runtime Khat and recipe), beside the
@@ -731,6 +762,9 @@ def main():
     if any(want(args, k, "assembly") for k in ("assembly_elastic_p1_3d", "assembly_laplace_p1_3d",
                                                 "coefficient_laplace_p1_3d")):
         assembly_legs(fei, meshgen, dev, args, legs, copy_gbs, acc)
+
+    if want(args, "iso_p2_3d", "forms"):
+        iso_leg(fei, meshgen, dev, args, legs, copy_gbs, acc)
 
     if want(args, "form_elastic_p1_3d", "forms"):
         form_leg(fei, meshgen, dev, args, legs, copy_gbs, acc, S)

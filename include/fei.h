@@ -187,6 +187,26 @@ int fei_integrate_coefficient(const fei_mesh *m, int form, const float *w, float
  * as [nb][nb][dim+1][dim][dim]; with K == NULL only *len is written.        */
 int fei_reference_tensor_coefficient(int form, int dim, float *K, int64_t *len);
 
+/* The isoparametric P2 Laplacian on elements with quadratic geometry (Sec.
+ * 3.1, eqs. 16-19): the geometry map and the solution basis are the P2 basis
+ * of the element's nodes; following the paper the inverse Jacobian is
+ * projected into a finite element space -- the vertex functions, by its
+ * values at the vertices -- and |J| is taken out of the integral as one
+ * constant, |det J| at the barycenter, so that
+ *   A_ij = G^{(k mu),(l nu)} K^{ijkl}_{mu nu},
+ *   G^{(k mu),(l nu)} = J^-1_{mu alpha,k} J^-1_{nu alpha,l} |J_c|,
+ * with the arity-4 reference tensor K^{ijkl}_{mu nu} = int_ref lambda_k
+ * dphi_i/dxi_mu lambda_l dphi_j/dxi_nu (exact, built with the library).
+ * Straight edges (edge nodes at the midpoints) give FEI_LAPLACE_P2 exactly.
+ *   m        dim 2 or 3, FP32 coordinates of all nodes (n_vertices = nodes),
+ *            conn device [E][nb] (nb = 6 or 10): the vertices, then the edge
+ *            nodes in the P2 order (0,1),(0,2),..
+ *   A        device [E][nb][nb] FP32, 16-byte aligned, overwritten
+ *   opt      precision FP32, store_rows 0; tau (applied to the Jacobians at
+ *            the vertices and the barycenter) and counters as for fei_integrate
+ * Asynchronous on `stream`.                                                 */
+int fei_integrate_iso(const fei_mesh *m, float *A, const fei_options *opt, void *stream);
+
 /* Adjoint of fei_integrate for L = sum_e <dA_e, A_e> (the reverse of the
  * chain A_e <- G_e <- (J^-1, |J|) <- vertex coordinates, Lame coefficients),
  * with G recomputed from the mesh rather than stored.

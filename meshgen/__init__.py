@@ -269,7 +269,7 @@ def _assert_positive_p2(coords: np.ndarray, conn: np.ndarray):
             raise AssertionError(f"{int((det <= 0).sum())} curved elements are inverted")
 
 
-def iso3d(n: int = 64, amp: float = 0.1) -> "Workload":
+def iso3d(n: int = 64, amp: float = 0.05) -> "Workload":
     """Isoparametric P2 Laplacian: the lap3d mesh (jittered Kuhn cube, 6 n^3
     tets) with quadratic geometry, edge nodes moved by up to amp times the
     edge length (curved edges)."""

@@ -24,7 +24,8 @@ import torch
 from . import _lib
 from ._lib import FORMS, PRECISIONS, FeiError
 
-__all__ = ["integrate", "integrate_adjoint", "integrate_coefficient", "element_matrices",
+__all__ = ["integrate", "integrate_adjoint", "integrate_coefficient", "integrate_iso",
+           "element_matrices",
            "local_size", "reference_tensor_coefficient",
            "reference_tensor", "reference_scale", "validate_mesh", "Batch", "Assembly", "FeiError",
            "FORMS", "PRECISIONS", "library_path"]
@@ -171,6 +172,40 @@ def integrate_coefficient(coords: torch.Tensor, conn: torch.Tensor, form: str, w
     o = _options("fp32", tau, counters, store_rows)
     _lib.check(lib.fei_integrate_coefficient(ctypes.byref(m), _form_id(form), _ptr(w), _ptr(out),
                                              ctypes.byref(o), _stream(dev)))
+    return out
+
+
+def integrate_iso(coords: torch.Tensor, conn: torch.Tensor, *, tau: float = 100.0,
+                  counters: Optional[torch.Tensor] = None,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Element matrices of the isoparametric P2 Laplacian (fei_integrate_iso):
+    ``coords`` [dim, N_nodes] float32, ``conn`` [E, nb] int32 (vertices then edge
+    nodes, nb = 6 in 2D, 10 in 3D); returns [E, nb, nb] float32."""
+    lib = _lib.load()
+    if coords.dim() != 2 or coords.shape[0] not in (2, 3):
+        raise ValueError("coords must be [dim, N_nodes] with dim 2 or 3")
+    dim = coords.shape[0]
+    nb = (dim + 1) * (dim + 2) // 2
+    dev = coords.device
+    if not coords.is_cuda:
+        raise ValueError("coords must be a device tensor (the library has no CPU path)")
+    _require(coords, "coords", torch.float32, dev)
+    _require(conn, "conn", torch.int32, dev)
+    if conn.dim() != 2 or conn.shape[1] != nb:
+        raise ValueError(f"conn must be [E, {nb}]")
+    m = _lib.FeiMesh()
+    m.dim, m.coord_dtype = dim, _lib.F32
+    m.n_vertices, m.n_elements = coords.shape[1], conn.shape[0]
+    m.x, m.y = coords[0].data_ptr(), coords[1].data_ptr()
+    m.z = coords[2].data_ptr() if dim == 3 else None
+    m.conn = conn.data_ptr()
+    E = conn.shape[0]
+    if out is None:
+        out = torch.empty((E, nb, nb), dtype=torch.float32, device=dev)
+    else:
+        _require(out, "out", torch.float32, dev, (E, nb, nb))
+    o = _options("fp32", tau, counters)
+    _lib.check(lib.fei_integrate_iso(ctypes.byref(m), out.data_ptr(), ctypes.byref(o), _stream(dev)))
     return out
 
 

@@ -26,7 +26,7 @@ NOALLOC_SCRATCH_BYTES = 96 * 1024 * 1024   # FEI_NOALLOC_SCRATCH_BYTES
 EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_default",
            "fei_local_size", "fei_reference_tensor", "fei_reference_scale", "fei_integrate",
            "fei_integrate_adjoint", "fei_integrate_adjoint_det", "fei_integrate_adjoint_det_noalloc",
-           "fei_integrate_coefficient",
+           "fei_integrate_coefficient", "fei_integrate_iso",
            "fei_reference_tensor_coefficient", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
            "fei_batch_run_adjoint", "fei_batch_tune", "fei_batch_get_config", "fei_batch_set_config",
            "fei_batch_copy_incidence", "fei_batch_destroy", "fei_assembly_create",
@@ -110,6 +110,7 @@ def load():
     lib.fei_integrate_adjoint_det_noalloc.argtypes = lib.fei_integrate_adjoint.argtypes
     lib.fei_integrate_coefficient.argtypes = [ctypes.POINTER(FeiMesh), ctypes.c_int, f32p, f32p,
                                               ctypes.POINTER(FeiOptions), vp]
+    lib.fei_integrate_iso.argtypes = [ctypes.POINTER(FeiMesh), f32p, ctypes.POINTER(FeiOptions), vp]
     lib.fei_reference_tensor_coefficient.argtypes = [ctypes.c_int, ctypes.c_int, vp,
                                                      ctypes.POINTER(i64)]
     lib.fei_validate_mesh.argtypes = [ctypes.POINTER(FeiMesh), ctypes.POINTER(i64), vp]

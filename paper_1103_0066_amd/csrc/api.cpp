@@ -389,6 +389,31 @@ int fei_integrate_coefficient(const fei_mesh *m, int form, const float *w, float
     return FEI_OK;
 }
 
+int fei_integrate_iso(const fei_mesh *m, float *A, const fei_options *opt, void *stream)
+{
+    MeshView mv;
+    int rc = check_mesh(m, mv);
+    if (rc) return rc;
+    if (m->coord_dtype != FEI_F32)
+        return fail(FEI_EUNSUPPORTED, "the isoparametric form takes FP32 coordinates");
+    fei_options o = opt ? *opt : defaults();
+    if ((rc = check_options(o))) return rc;
+    if (o.precision != FEI_PREC_FP32)
+        return fail(FEI_EUNSUPPORTED, "the isoparametric form contracts in FP32");
+    if (o.store_rows != 0)
+        return fail(FEI_EUNSUPPORTED, "the isoparametric form stages whole matrices");
+    if (m->n_elements == 0) return FEI_OK;
+    if (!A || !aligned(A, 16)) return fail(FEI_EINVAL, "A NULL or not 16-byte aligned");
+    FwdParams p;
+    p.m = mv;
+    p.mu = p.lam = p.w = nullptr;
+    p.A = A;
+    p.counters = o.counters;
+    p.tau2 = tau2_of(o.tau);
+    hipError_t e = launch_iso(m->dim, p, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FEI_OK : hip_fail(e, "isoparametric launch");
+}
+
 int fei_reference_tensor_coefficient(int form, int dim, float *K, int64_t *len)
 {
     if (!len) return fail(FEI_EINVAL, "len is NULL");

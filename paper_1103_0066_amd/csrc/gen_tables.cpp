@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <vector>
 
+#include "polyint.h"
 #include "shapes.h"
 
 using namespace fei;
@@ -125,6 +126,54 @@ static void emit_form()
     emit_frags<F, D, P_BF16X3>();
 }
 
+// Isoparametric P2 Laplacian: K^{ijkl}_{mu nu} = int_ref lambda_k dphi_i/dxi_mu
+// lambda_l dphi_j/dxi_nu (eq. 18, the inverse Jacobian projected on the vertex
+// functions lambda_k), exactly, folded over the symmetric pairs of G:
+// Kf[(i,j)][(p,q)] = K_ij^{pq} + [p != q] K_ij^{qp}, as integers over their
+// common denominator.
+template <int D>
+static void emit_iso()
+{
+    using S = IsoShape<D>;
+    using namespace fei::poly;
+    const std::vector<Poly> B = lagrange_basis(D, 2);
+    std::vector<Poly> P(size_t(S::GD) * S::NB);           // [p = k D + mu][i]
+    for (int k = 0; k < S::NV; ++k) {
+        Poly lk;
+        Mono m{};
+        m[k] = 1;
+        add_term(lk, m, Rat(1));
+        for (int mu = 0; mu < D; ++mu)
+            for (int i = 0; i < S::NB; ++i) P[size_t(k * D + mu) * S::NB + i] = mul(lk, dxi(B[i], mu));
+    }
+    auto K = [&](int i, int j, int p, int q) {
+        return integrate_ref(mul(P[size_t(p) * S::NB + i], P[size_t(q) * S::NB + j]), D);
+    };
+    std::vector<Rat> Kf(size_t(S::NU) * S::G);
+    int64_t lcd = 1;
+    for (int i = 0; i < S::NB; ++i)
+        for (int j = i; j < S::NB; ++j)
+            for (int p = 0; p < S::GD; ++p)
+                for (int q = p; q < S::GD; ++q) {
+                    Rat v = K(i, j, p, q);
+                    if (p != q) v = v + K(i, j, q, p);
+                    Kf[size_t(sym_index(S::NB, i, j)) * S::G + sym_index(S::GD, p, q)] = v;
+                    lcd = lcd / std::gcd(lcd, v.q) * v.q;
+                }
+    std::printf("template <> struct KIsoFold<%d> {\n"
+                "    static constexpr KIsoTable<%d> t = {{", D, D);
+    int n = 0;
+    for (const Rat &v : Kf) {
+        const int64_t iv = v.p * (lcd / v.q);
+        if (iv >= (int64_t(1) << 24) || -iv >= (int64_t(1) << 24)) {
+            std::fprintf(stderr, "isoparametric K entry %lld not exact in FP32\n", (long long)iv);
+            std::exit(1);
+        }
+        std::printf("%s%lld.f", sep(n++), (long long)iv);
+    }
+    std::printf("}, %.17g};\n};\n", 1.0 / double(lcd));
+}
+
 int main()
 {
     std::printf("// Generated by gen_tables.cpp at build time. Do not edit.\n");
@@ -139,6 +188,8 @@ int main()
     emit_coefficient<WLAP1, 3>();
     emit_coefficient<WLAP2, 2>();
     emit_coefficient<WLAP2, 3>();
+    emit_iso<2>();
+    emit_iso<3>();
     std::printf("}  // namespace fei\n");
     return 0;
 }

@@ -11,6 +11,7 @@
 #include "gather.h"
 #include "fwd_coef.h"
 #include "fwd_form.h"
+#include "fwd_iso.h"
 #include "fwd_fma.h"
 #include "fwd_mfma.h"
 
@@ -545,6 +546,19 @@ hipError_t launch_form(int dim, int degree, int ncomp, bool sym, bool noval, con
         if (degree == 2) return vec ? launch_form_sym<3, 2, 3>(sym, noval, p, s) : launch_form_sym<3, 2, 1>(sym, noval, p, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_iso(int dim, const FwdParams &p, hipStream_t s)
+{
+    const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
+    if (n_groups == 0) return hipSuccess;
+    if (dim == 3)
+        hipLaunchKernelGGL(iso_kernel<3>, dim3(unsigned(n_groups)), dim3(kBlock), 0, s, p);
+    else if (dim == 2)
+        hipLaunchKernelGGL(iso_kernel<2>, dim3(unsigned(n_groups)), dim3(kBlock), 0, s, p);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 }  // namespace fei

@@ -135,6 +135,10 @@ hipError_t launch_vertex_gather_one(const GatherItem &it, hipStream_t s);
 hipError_t launch_validate(const MeshView &m, int dim, unsigned long long *n_bad_dev,
                            hipStream_t s);
 
+// Isoparametric P2 Laplacian (quadratic geometry): m.conn is [E][NB] (the
+// element's P2 nodes), m.x/y/z the node coordinates (FP32).
+hipError_t launch_iso(int dim, const FwdParams &p, hipStream_t s);
+
 // Runtime-described bilinear forms (form front end): the geometric tensor
 // G = |J| That^T C_e That from the operator tables W and per-element
 // coefficients, contracted with the reference tensor Khat.

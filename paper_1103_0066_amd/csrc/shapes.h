@@ -58,6 +58,28 @@ struct KSparse {
     float coef[Traits<FORM, DIM>::G][KSparseShape<FORM, DIM>::NNZ];
 };
 
+// Isoparametric P2 Laplacian (Sec. 3.1, eqs. 16-19): quadratic geometry and
+// basis (NB nodes), the inverse Jacobian projected on the NV vertex functions.
+// G^{(k mu),(l nu)} pairs p = k DIM + mu (GD of them, G unique); unique entries
+// (i <= j) of the NB x NB element matrix: NU.
+template <int DIM>
+struct IsoShape {
+    static constexpr int NV = DIM + 1;
+    static constexpr int NB = (DIM + 1) * (DIM + 2) / 2;
+    static constexpr int GD = NV * DIM;
+    static constexpr int G = GD * (GD + 1) / 2;
+    static constexpr int NU = NB * (NB + 1) / 2;
+};
+
+// Folded arity-4 reference tensor: v[u * G + g] for unique entry u = (i <= j)
+// and unique pair g = (p <= q), integers over a common denominator; the
+// tensor is v * scale.
+template <int DIM>
+struct KIsoTable {
+    float v[IsoShape<DIM>::NU * IsoShape<DIM>::G];
+    double scale;
+};
+
 FEI_HD constexpr void sym_pair(int gd, int gamma, int &p, int &q)
 {
     for (int i = 0; i < gd; ++i)

@@ -308,3 +308,17 @@ def test_noalloc_adjoint_rejects_oversized_meshes_without_device_work():
     m = _fake_mesh(E=0)                                  # E = 0: a no-op
     assert lib.fei_integrate_adjoint_det_noalloc(ctypes.byref(m), 1, None, None, None, None, None,
                                                  None, None, None, None, None) == 0
+
+
+def test_iso_entry_point_rejects_without_device_work():
+    lib = _lib.load()
+    o = _opts()
+    m = _fake_mesh(E=0)
+    assert lib.fei_integrate_iso(ctypes.byref(m), None, ctypes.byref(o), None) == 0
+    m = _fake_mesh(dtype=_lib.F64)
+    assert lib.fei_integrate_iso(ctypes.byref(m), FAKE, ctypes.byref(o), None) == _lib.FEI_EUNSUPPORTED
+    m = _fake_mesh()
+    assert lib.fei_integrate_iso(ctypes.byref(m), None, ctypes.byref(o), None) == _lib.FEI_EINVAL
+    assert lib.fei_integrate_iso(ctypes.byref(m), FAKE + 4, ctypes.byref(o), None) == _lib.FEI_EINVAL
+    o2 = _opts(precision=1)
+    assert lib.fei_integrate_iso(ctypes.byref(m), FAKE, ctypes.byref(o2), None) == _lib.FEI_EUNSUPPORTED
