@@ -129,7 +129,14 @@ typedef struct fei_options {
                                or R = n (whole matrices, staged 64 or 32
                                elements at a time); FEI_EUNSUPPORTED
                                otherwise. */
-    int32_t reserved[4];    /* must be zero */
+    int32_t block_elements; /* forward, FP32 contraction, default staging:
+                               elements per workgroup (the paper's element
+                               batch size, Sec. 4), 64, 128, 256 or 512;
+                               0 = the tune table's choice for this form, dim,
+                               precision and size (fei_tune_forward), else 256.
+                               FEI_EUNSUPPORTED for other precisions or
+                               staging with a value other than 0 or 256. */
+    int32_t reserved[3];    /* must be zero */
 } fei_options;
 
 /* Version of this ABI (FEI_ABI_VERSION). */
@@ -255,6 +262,40 @@ int fei_integrate_adjoint_det_noalloc(const fei_mesh *m, int form, const float *
                                       const float *lam, const float *dA, float *dx, float *dy,
                                       float *dz, float *dmu, float *dlam,
                                       const fei_options *opt, void *stream);
+
+/* ---- tuning ------------------------------------------------------------------
+ * A process-wide tune table maps (form, dim, precision, coordinate type, size
+ * bucket = floor(log2 E)) to the forward's elements per workgroup and output
+ * staging; fei_integrate consults it when opt->block_elements and
+ * opt->store_rows are both 0.  If the environment variable FEI_TUNE_FILE names
+ * a file, the table is loaded from it on first use.                          */
+typedef struct fei_tune_result {
+    int32_t block_elements;     /* chosen elements per workgroup */
+    int32_t store_rows;         /* chosen staging (0: the form's default) */
+    float ms;                   /* its mean time per launch */
+    int32_t candidates;         /* configurations timed */
+} fei_tune_result;
+
+/* Times the forward's candidate configurations (elements per workgroup 64,
+ * 128, 256, 512 and the staging variants for FP32; staged or direct stores
+ * for the MFMA precisions) on the caller's data -- A is written by every
+ * trial -- records the fastest in the tune table and returns it in *out (if
+ * not NULL).  Arguments as for fei_integrate (opt->block_elements and
+ * opt->store_rows are ignored).  Synchronizes `stream`.                     */
+int fei_tune_forward(const fei_mesh *m, int form, const float *mu, const float *lam, float *A,
+                     const fei_options *opt, void *stream, fei_tune_result *out);
+/* The table's entry for a call, if any: returns 1 and fills *out when present,
+ * 0 when not.  Host-only.                                                    */
+int fei_tune_lookup(int form, int dim, int precision, int coord_dtype, int64_t n_elements,
+                    fei_tune_result *out);
+/* Writes the table as JSON lines ({"arch": .., "form": .., "dim": .., "precision": ..,
+ * "coord": .., "ebucket": .., "block_elements": .., "store_rows": .., "ms": ..}),
+ * or reads such a file and merges its entries (entries of another GPU
+ * architecture are skipped when a device is present).  Host-only.          */
+int fei_tune_save(const char *path);
+int fei_tune_load(const char *path);
+/* Empties the table.                                                         */
+int fei_tune_clear(void);
 
 /* Checks conn against n_vertices on the device and returns the number of
  * out-of-range entries in *n_bad.  Synchronises the stream.                 */

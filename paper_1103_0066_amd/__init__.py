@@ -25,7 +25,8 @@ from . import _lib
 from ._lib import FORMS, PRECISIONS, FeiError
 
 __all__ = ["integrate", "integrate_adjoint", "integrate_coefficient", "integrate_iso",
-           "element_matrices",
+           "element_matrices", "tune_forward", "tune_lookup", "tune_save", "tune_load",
+           "tune_clear",
            "local_size", "reference_tensor_coefficient",
            "reference_tensor", "reference_scale", "validate_mesh", "Batch", "Assembly", "FeiError",
            "FORMS", "PRECISIONS", "library_path"]
@@ -109,7 +110,7 @@ def _mesh(coords: torch.Tensor, conn: torch.Tensor) -> _lib.FeiMesh:
 
 
 def _options(precision: str, tau: float, counters: Optional[torch.Tensor],
-             store_rows: int = 0) -> _lib.FeiOptions:
+             store_rows: int = 0, block_elements: int = 0) -> _lib.FeiOptions:
     o = _lib.FeiOptions()
     _lib.check(_lib.load().fei_options_default(ctypes.byref(o)))
     try:
@@ -118,6 +119,7 @@ def _options(precision: str, tau: float, counters: Optional[torch.Tensor],
         raise ValueError(f"unknown precision {precision!r}") from None
     o.tau = float(tau)
     o.store_rows = int(store_rows)
+    o.block_elements = int(block_elements)
     if counters is not None:
         _require(counters, "counters", torch.int32, counters.device, (2,))
         o.counters = counters.data_ptr()
@@ -132,10 +134,12 @@ def integrate(coords: torch.Tensor, conn: torch.Tensor, form: str,
               mu: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None, *,
               precision: str = "fp32", tau: float = 100.0,
               counters: Optional[torch.Tensor] = None,
-              out: Optional[torch.Tensor] = None, store_rows: int = 0) -> torch.Tensor:
+              out: Optional[torch.Tensor] = None, store_rows: int = 0,
+              block_elements: int = 0) -> torch.Tensor:
     """Element matrices A[e] = G_e : K (no autograd).  ``counters`` (int32[2],
     device) accumulates [elements on the FP64 path, elements with det J == 0].
-    ``store_rows`` selects the output staging (fei_options.store_rows)."""
+    ``store_rows`` selects the output staging (fei_options.store_rows),
+    ``block_elements`` the elements per workgroup (0: the tune table's choice)."""
     lib = _lib.load()
     m = _mesh(coords, conn)
     dev = coords.device
@@ -148,10 +152,56 @@ def integrate(coords: torch.Tensor, conn: torch.Tensor, form: str,
         out = torch.empty((E, n, n), dtype=torch.float32, device=dev)
     else:
         _require(out, "out", torch.float32, dev, (E, n, n))
-    o = _options(precision, tau, counters, store_rows)
+    o = _options(precision, tau, counters, store_rows, block_elements)
     _lib.check(lib.fei_integrate(ctypes.byref(m), _form_id(form), _ptr(mu), _ptr(lam),
                                  _ptr(out), ctypes.byref(o), _stream(dev)))
     return out
+
+
+def _tune_dict(r: "_lib.FeiTuneResult") -> dict:
+    return {"block_elements": r.block_elements, "store_rows": r.store_rows, "ms": r.ms,
+            "candidates": r.candidates}
+
+
+def tune_forward(coords: torch.Tensor, conn: torch.Tensor, form: str,
+                 mu: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None, *,
+                 precision: str = "fp32", tau: float = 100.0,
+                 out: Optional[torch.Tensor] = None) -> dict:
+    """Times the forward's launch shapes on this mesh (fei_tune_forward), records
+    the fastest in the tune table (used by integrate(..., block_elements=0,
+    store_rows=0) for this form, dim, precision and size) and returns it."""
+    lib = _lib.load()
+    m = _mesh(coords, conn)
+    dev = coords.device
+    n = local_size(form, m.dim)
+    if out is None:
+        out = torch.empty((m.n_elements, n, n), dtype=torch.float32, device=dev)
+    o = _options(precision, tau, None)
+    r = _lib.FeiTuneResult()
+    _lib.check(lib.fei_tune_forward(ctypes.byref(m), _form_id(form), _ptr(mu), _ptr(lam),
+                                    _ptr(out), ctypes.byref(o), _stream(dev), ctypes.byref(r)))
+    return _tune_dict(r)
+
+
+def tune_lookup(form: str, dim: int, precision: str, n_elements: int,
+                coord_dtype: torch.dtype = torch.float32) -> Optional[dict]:
+    r = _lib.FeiTuneResult()
+    f = _lib.F64 if coord_dtype == torch.float64 else _lib.F32
+    hit = _lib.load().fei_tune_lookup(_form_id(form), dim, PRECISIONS[precision], f,
+                                      int(n_elements), ctypes.byref(r))
+    return _tune_dict(r) if hit == 1 else None
+
+
+def tune_save(path: str) -> None:
+    _lib.check(_lib.load().fei_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    _lib.check(_lib.load().fei_tune_load(path.encode()))
+
+
+def tune_clear() -> None:
+    _lib.check(_lib.load().fei_tune_clear())
 
 
 def integrate_coefficient(coords: torch.Tensor, conn: torch.Tensor, form: str, w: torch.Tensor, *,

@@ -32,7 +32,8 @@ EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_d
            "fei_batch_copy_incidence", "fei_batch_destroy", "fei_assembly_create",
            "fei_assembly_info", "fei_assembly_copy_pattern", "fei_assemble",
            "fei_assembly_destroy", "fei_form_create", "fei_form_info", "fei_form_reference_tensor",
-           "fei_form_integrate", "fei_form_destroy")
+           "fei_form_integrate", "fei_form_destroy", "fei_tune_forward", "fei_tune_lookup",
+           "fei_tune_save", "fei_tune_load", "fei_tune_clear")
 
 
 class FeiMesh(ctypes.Structure):
@@ -45,7 +46,12 @@ class FeiMesh(ctypes.Structure):
 class FeiOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tau", ctypes.c_float),
                 ("counters", ctypes.c_void_p), ("store_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("block_elements", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class FeiTuneResult(ctypes.Structure):
+    _fields_ = [("block_elements", ctypes.c_int32), ("store_rows", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("candidates", ctypes.c_int32)]
 
 
 class FeiBatchItem(ctypes.Structure):
@@ -137,6 +143,12 @@ def load():
     lib.fei_form_integrate.argtypes = [vp, ctypes.POINTER(FeiMesh), f32p, f32p,
                                        ctypes.POINTER(FeiOptions), vp]
     lib.fei_form_destroy.argtypes = [vp]
+    lib.fei_tune_forward.argtypes = [ctypes.POINTER(FeiMesh), ctypes.c_int, f32p, f32p, f32p,
+                                     ctypes.POINTER(FeiOptions), vp, ctypes.POINTER(FeiTuneResult)]
+    lib.fei_tune_lookup.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, i64,
+                                    ctypes.POINTER(FeiTuneResult)]
+    lib.fei_tune_save.argtypes = [ctypes.c_char_p]
+    lib.fei_tune_load.argtypes = [ctypes.c_char_p]
     for name in EXPORTS:
         getattr(lib, name)
     _lib = lib

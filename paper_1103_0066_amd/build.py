@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
         f.write(tables)
     os.replace(tmp, os.path.join(GEN, "tables.inc"))
 
-    sources = ["kernels.hip", "api.cpp", "batch.cpp", "assembly.cpp", "noalloc.cpp", "forms.cpp"]
+    sources = ["kernels.hip", "api.cpp", "batch.cpp", "assembly.cpp", "noalloc.cpp", "forms.cpp", "tune.cpp"]
     objs = [os.path.join(GEN, os.path.splitext(s)[0] + ".o") for s in sources]
 
     def compile_one(args):

@@ -67,6 +67,10 @@ int check_options(const fei_options &o)
     if (std::isnan(o.tau)) return fail(FEI_EINVAL, "tau is NaN");
     for (int r : o.reserved)
         if (r != 0) return fail(FEI_EINVAL, "fei_options.reserved must be zero");
+    if (o.block_elements != 0 && o.block_elements != 64 && o.block_elements != 128 &&
+        o.block_elements != 256 && o.block_elements != 512)
+        return fail(FEI_EINVAL, "block_elements must be 0, 64, 128, 256 or 512 (got %d)",
+                    o.block_elements);
     if (o.counters && !aligned(o.counters, 4)) return fail(FEI_EINVAL, "counters misaligned");
     return FEI_OK;
 }
@@ -339,7 +343,15 @@ int fei_integrate(const fei_mesh *m, int form, const float *mu, const float *lam
     if (m->n_elements == 0) return FEI_OK;
     if (!A) return fail(FEI_EINVAL, "A is NULL");
     if (!aligned(A, 16)) return fail(FEI_EINVAL, "A must be 16-byte aligned");
-    const Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision, o.store_rows};
+    Variant v{form, m->dim, m->coord_dtype == FEI_F64, o.precision, o.store_rows, 0,
+              o.block_elements};
+    if (o.block_elements == 0 && o.store_rows == 0) {
+        fei_tune_result t;
+        if (tune_find(form, m->dim, o.precision, m->coord_dtype, m->n_elements, t)) {
+            v.block = t.block_elements;
+            v.rows = t.store_rows;
+        }
+    }
     FwdLauncher launch = find_forward(v);
     if (!launch) return fail(FEI_EUNSUPPORTED, "no forward kernel for this variant");
     FwdParams p;

@@ -71,7 +71,7 @@ struct fei_batch {
     int precision = 0;
     Side side[2];
     Gather gather;
-    int32_t *d_counter = nullptr;  // [0] forward, [1] adjoint
+    int32_t *d_counter = nullptr;  // [0, 8) forward, [8, 16) adjoint work counters
     hipStream_t cap = nullptr;
     hipStream_t branch[6] = {};
     hipEvent_t fork = nullptr;
@@ -139,7 +139,8 @@ hipError_t enqueue(fei_batch *b, int adj, const fei_batch_config &c, hipStream_t
     const BatchItemDev *grouped = gather ? sd.d_grouped_g : sd.d_grouped;
     hipError_t e = hipSuccess;
     if (c.mode == 0) {
-        BatchLaunch L{all, int32_t(sd.all.size()), c.tiles_per_pop, sd.tiles, b->d_counter + adj};
+        BatchLaunch L{all, int32_t(sd.all.size()), c.tiles_per_pop, sd.tiles,
+                      b->d_counter + kBatchCounters * adj};
         if ((e = launch_batch_reset(L.counter, s)) != hipSuccess) return e;
         if ((e = launch_batch(adj != 0, prec, c.variant, L, c.workgroups, s)) != hipSuccess) return e;
     } else {
@@ -448,11 +449,11 @@ int fei_batch_create(const fei_batch_item *items, int n_items, const fei_options
         sd.cfg.tiles_per_pop = 1;
         sd.cfg.ms = 0.f;
     }
-    if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_counter), 2 * sizeof(int32_t))) != hipSuccess) {
+    if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_counter), 2 * kBatchCounters * sizeof(int32_t))) != hipSuccess) {
         release(b);
         return fail(FEI_ENOMEM, "work counter: %s", hipGetErrorString(e));
     }
-    if ((e = hipMemset(b->d_counter, 0, 2 * sizeof(int32_t))) == hipSuccess &&
+    if ((e = hipMemset(b->d_counter, 0, 2 * kBatchCounters * sizeof(int32_t))) == hipSuccess &&
         (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) == hipSuccess &&
         (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) == hipSuccess) {
         for (int g = 0; g < 6 && e == hipSuccess; ++g) {

@@ -119,25 +119,37 @@ __device__ __forceinline__ void batch_adj_dispatch(const BatchItemDev &d, int64_
     }
 }
 
-// Persistent loop shared by the forward and adjoint kernels.  Every
-// workgroup exits once the counter has passed the last tile.
+// Persistent loop shared by the forward and adjoint kernels.  The tiles are
+// split into kBatchCounters contiguous ranges, each with its own work counter
+// (one device-wide counter serialized every pop at the memory side).  A
+// workgroup starts on the range of its XCD (workgroups are dispatched
+// round-robin over the 8 XCDs, blockIdx mod 8) and, once that range is
+// drained, takes tiles from the following ranges in turn; every tile is taken
+// exactly once (one atomic per pop), and every workgroup exits after finding
+// all ranges drained -- also when fewer than 8 workgroups run.
 template <bool ADJ, int PREC, int VAR>
 __device__ __forceinline__ void batch_loop(const BatchLaunch &b, unsigned char *smem)
 {
     __shared__ long long s_tile;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(b.counter, b.tiles_per_pop);
-        __syncthreads();
-        const int64_t t0 = s_tile;
-        __syncthreads();
-        if (t0 >= b.n_tiles) break;
-        const int64_t t1 = (t0 + b.tiles_per_pop < b.n_tiles) ? t0 + b.tiles_per_pop : b.n_tiles;
-        for (int64_t t = t0; t < t1; ++t) {
-            const int it = batch_find_item(b, t);
-            const BatchItemDev &d = b.items[it];
-            if constexpr (ADJ) batch_adj_dispatch<VAR>(d, t - d.tile_begin, smem);
-            else batch_fwd_dispatch<PREC, VAR>(d, t - d.tile_begin, smem);
-            __syncthreads();  // LDS is reused by the next tile
+    const int x0 = int(blockIdx.x % kBatchCounters);
+    for (int hop = 0; hop < kBatchCounters; ++hop) {
+        const int x = (x0 + hop) % kBatchCounters;
+        const int64_t r0 = x * b.n_tiles / kBatchCounters;
+        const int64_t r1 = (x + 1) * b.n_tiles / kBatchCounters;
+        for (;;) {
+            if (threadIdx.x == 0) s_tile = r0 + atomicAdd(b.counter + x, b.tiles_per_pop);
+            __syncthreads();
+            const int64_t t0 = s_tile;
+            __syncthreads();
+            if (t0 >= r1) break;
+            const int64_t t1 = (t0 + b.tiles_per_pop < r1) ? t0 + b.tiles_per_pop : r1;
+            for (int64_t t = t0; t < t1; ++t) {
+                const int it = batch_find_item(b, t);
+                const BatchItemDev &d = b.items[it];
+                if constexpr (ADJ) batch_adj_dispatch<VAR>(d, t - d.tile_begin, smem);
+                else batch_fwd_dispatch<PREC, VAR>(d, t - d.tile_begin, smem);
+                __syncthreads();  // LDS is reused by the next tile
+            }
         }
     }
 }
@@ -177,7 +189,7 @@ __global__ __launch_bounds__(256) void batch_group_kernel(BatchLaunch b)
 // Work-counter reset as a kernel node (graphs get no memset nodes).
 __global__ void batch_reset_kernel(int32_t *counter)
 {
-    if (threadIdx.x == 0) counter[0] = 0;
+    if (threadIdx.x < kBatchCounters) counter[threadIdx.x] = 0;
 }
 
 }  // namespace fei

@@ -328,14 +328,19 @@ struct FwdFmaTile {
         }
     }
 
-    // The whole tile in order (batch kernels).
-    __device__ __forceinline__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    // The wave's 64 elements from e0 (LDS_BYTES / 4 bytes of smem per wave).
+    __device__ __forceinline__ static void run_at(const FwdParams &p, int64_t e0, unsigned char *smem)
     {
-        const int64_t e0 = blk * 256 + wave_id() * 64;
         const Xv g = gather_xv(p, e0, load(p, e0));
         float Au[U::NU];
         compute(p, e0, g, Au);
         store(p, e0, Au, smem);
+    }
+
+    // The whole 256-element tile blk in order (batch kernels).
+    __device__ __forceinline__ static void run(const FwdParams &p, int64_t blk, unsigned char *smem)
+    {
+        run_at(p, blk * 256 + wave_id() * 64, smem);
     }
 };
 
@@ -365,12 +370,16 @@ struct PersistentTiles {
 // below 76 KB), so the hardware overlaps one workgroup's gathers and
 // contraction with another's stores; measured faster on MI355X than a
 // persistent, software-pipelined loop over tiles with one wave per SIMD.
-template <int FORM, int DIM, typename CT, int R>
-__global__ __launch_bounds__(256) void fwd_fma_kernel(FwdParams p)
+//
+// WAVES: waves per workgroup (64 WAVES elements per workgroup; the paper's
+// element batch size, Sec. 4, a tuning axis: 4 by default).
+template <int FORM, int DIM, typename CT, int R, int WAVES = 4>
+__global__ __launch_bounds__(64 * WAVES) void fwd_fma_kernel(FwdParams p)
 {
     using Tile = FwdFmaTile<FORM, DIM, CT, R>;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES > 0 ? Tile::LDS_BYTES : 16];
-    Tile::run(p, xcd_block(blockIdx.x, gridDim.x), smem);
+    constexpr int LDS = Tile::LDS_BYTES / 4 * WAVES;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS > 0 ? LDS : 16];
+    Tile::run_at(p, xcd_block(blockIdx.x, gridDim.x) * (64 * WAVES) + wave_id() * 64, smem);
 }
 
 }  // namespace fei

@@ -41,5 +41,9 @@ int check_det(const fei_mesh *m, Variant &v);
 int enqueue_adjoint_det(AdjParams p, const Variant &v, void *base, const DetLayout &L,
                         hipStream_t s);
 
+// Tune table (tune.cpp): the entry for a forward call, if any.
+bool tune_find(int form, int dim, int precision, int coord_dtype, int64_t n_elements,
+               fei_tune_result &out);
+
 }  // namespace host
 }  // namespace fei

@@ -51,12 +51,13 @@ hipError_t launch_persistent(const P &p, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int F, int D, typename CT, int R>
+template <int F, int D, typename CT, int R, int WAVES = 4>
 hipError_t launch_fwd_fma(const FwdParams &p, hipStream_t s)
 {
-    const int64_t n_groups = (p.m.n_elements + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL((fwd_fma_kernel<F, D, CT, R>), dim3(unsigned(n_groups)), dim3(kBlock), 0, s,
-                       p);
+    const int64_t per = 64 * WAVES;
+    const int64_t n_groups = (p.m.n_elements + per - 1) / per;
+    hipLaunchKernelGGL((fwd_fma_kernel<F, D, CT, R, WAVES>), dim3(unsigned(n_groups)),
+                       dim3(unsigned(per)), 0, s, p);
     return hipGetLastError();
 }
 
@@ -197,9 +198,26 @@ AdjLauncher adj_fma_rows(int rows)
     }
 }
 
+// Elements per workgroup other than 256 (FP32 coordinates, default staging).
+template <int F, int D>
+FwdLauncher fwd_fma_block(int block)
+{
+    constexpr int R = default_rows<F, D>();
+    switch (block) {
+    case 64: return &launch_fwd_fma<F, D, float, R, 1>;
+    case 128: return &launch_fwd_fma<F, D, float, R, 2>;
+    case 512: return &launch_fwd_fma<F, D, float, R, 8>;
+    default: return nullptr;
+    }
+}
+
 template <int F, int D, typename CT>
 FwdLauncher fwd_for_prec(const Variant &v)
 {
+    if (v.block != 0 && v.block != 256) {
+        if (v.precision != P_FP32 || v.rows != 0 || !std::is_same<CT, float>::value) return nullptr;
+        return fwd_fma_block<F, D>(v.block);
+    }
     if (v.precision == P_FP32) return fwd_fma_rows<F, D, CT>(v.rows);
     // MFMA form: staged stores of whole matrices (0, or rows = n), or direct (-1)
     const bool direct = v.rows < 0;

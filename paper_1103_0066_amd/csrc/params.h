@@ -44,6 +44,7 @@ struct Variant {
     int precision;  // fei_precision
     int rows;       // fei_options.store_rows: 0 default, -1 direct, R > 0 staged
     int gather;     // adjoint: 1 writes J-bar (AdjParams.jbar) and has no vertex scatter
+    int block;      // forward: elements per workgroup (0 = 256)
 };
 
 using FwdLauncher = hipError_t (*)(const FwdParams &, hipStream_t);
@@ -67,12 +68,16 @@ struct BatchItemDev {
     AdjParams ap;
 };
 
+// Work counters of the persistent batch kernel: one per contiguous range of
+// tiles (one range per XCD).
+constexpr int kBatchCounters = 8;
+
 struct BatchLaunch {
     const BatchItemDev *items;  // device, sorted by tile_begin
     int32_t n_items;
     int32_t tiles_per_pop;
     int64_t n_tiles;
-    int32_t *counter;           // device work counter, reset by launch_batch_reset
+    int32_t *counter;           // device work counters [kBatchCounters], reset by launch_batch_reset
 };
 
 // Dynamic LDS bytes of a batch kernel variant; 0 if the variant does not exist.

@@ -322,3 +322,56 @@ def test_iso_entry_point_rejects_without_device_work():
     assert lib.fei_integrate_iso(ctypes.byref(m), FAKE + 4, ctypes.byref(o), None) == _lib.FEI_EINVAL
     o2 = _opts(precision=1)
     assert lib.fei_integrate_iso(ctypes.byref(m), FAKE, ctypes.byref(o2), None) == _lib.FEI_EUNSUPPORTED
+
+
+def test_tune_table_round_trip_and_lookup(tmp_path):
+    """The tune table (host-only): a JSON-lines file loads, answers lookups by
+    size bucket, saves back, and malformed lines are reported."""
+    lib = _lib.load()
+    lib.fei_tune_clear()
+    src = tmp_path / "tune.jsonl"
+    src.write_text('{"form": 2, "dim": 3, "precision": 0, "coord": 0, "ebucket": 20, '
+                   '"block_elements": 512, "store_rows": 0, "ms": 0.2}\n'
+                   '{"form": 1, "dim": 3, "precision": 1, "coord": 0, "ebucket": 20, '
+                   '"block_elements": 256, "store_rows": -1, "ms": 0.05}\n')
+    assert lib.fei_tune_load(str(src).encode()) == 0
+    r = _lib.FeiTuneResult()
+    assert lib.fei_tune_lookup(2, 3, 0, 0, 1572864, ctypes.byref(r)) == 1     # 2^20 <= E < 2^21
+    assert (r.block_elements, r.store_rows) == (512, 0)
+    assert lib.fei_tune_lookup(2, 3, 0, 0, 3 * 2 ** 20, ctypes.byref(r)) == 0  # other bucket
+    assert lib.fei_tune_lookup(1, 3, 1, 0, 2 ** 20, ctypes.byref(r)) == 1 and r.store_rows == -1
+    dst = tmp_path / "out.jsonl"
+    assert lib.fei_tune_save(str(dst).encode()) == 0
+    lines = dst.read_text().splitlines()
+    assert len(lines) == 2 and all('"block_elements"' in l for l in lines)
+    lib.fei_tune_clear()
+    assert lib.fei_tune_lookup(2, 3, 0, 0, 1572864, ctypes.byref(r)) == 0
+    assert lib.fei_tune_load(str(dst).encode()) == 0
+    assert lib.fei_tune_lookup(2, 3, 0, 0, 1572864, ctypes.byref(r)) == 1
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"form": 2, "dim": 3}\n')
+    assert lib.fei_tune_load(str(bad).encode()) == _lib.FEI_EINVAL
+    assert lib.fei_tune_load(str(tmp_path / "missing").encode()) == _lib.FEI_EINVAL
+    lib.fei_tune_clear()
+
+
+def test_tune_file_from_environment(tmp_path):
+    """FEI_TUNE_FILE is read on first use of the table (a fresh process)."""
+    import subprocess
+    import sys
+    src = tmp_path / "env.jsonl"
+    src.write_text('{"form": 3, "dim": 3, "precision": 0, "coord": 0, "ebucket": 10, '
+                   '"block_elements": 128, "store_rows": 0, "ms": 0.01}\n')
+    code = ("import ctypes, sys; sys.path.insert(0, %r)\n"
+            "from paper_1103_0066_amd import _lib\n"
+            "lib = _lib.load(); r = _lib.FeiTuneResult()\n"
+            "print(lib.fei_tune_lookup(3, 3, 0, 0, 1500, ctypes.byref(r)), r.block_elements)\n" % ROOT)
+    env = dict(os.environ, FEI_TUNE_FILE=str(src))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=120)
+    assert out.stdout.split() == ["1", "128"], out.stderr
+
+
+def test_block_elements_is_validated():
+    m = _fake_mesh()
+    assert _call(m, opt=_opts(block_elements=96)) == _lib.FEI_EINVAL
