@@ -222,7 +222,17 @@ int fei_integrate_iso(const fei_mesh *m, float *A, const fei_options *opt, void 
  *               dz is NULL in 2D.  The caller zeroes them first if needed.
  *               Summation order is not deterministic.
  *   dmu, dlam   device [E] FP32, overwritten (FEI_ELASTIC_P1 only; NULL skips)
- * Only FEI_PREC_FP32 is accepted for the adjoint.                           */
+ *   opt         precision: FEI_PREC_FP32 (default), or FEI_PREC_FP16X2 /
+ *               BF16X2 / BF16X3: the fold of dA with K (the contraction of
+ *               eq. 1 in reverse, U_g = sum_ij Kf[g][ij] dA_ij) runs on the
+ *               matrix cores with dA split into two or three 16-bit terms
+ *               (FP16 with a power-of-two scale per element); K is exact in
+ *               both formats, so only dA carries split error (FP16x2 and
+ *               BF16x3 about FP32's, BF16x2 about 2^-16 of the largest
+ *               entry).  These need FP32 coordinates, store_rows 0 or n, and
+ *               n*n a multiple of 4 (FEI_EUNSUPPORTED for the 3 x 3 matrices
+ *               of the 2D P1 Laplacian).  Elements flagged by the quality
+ *               test fold in FP64 in every precision.                        */
 int fei_integrate_adjoint(const fei_mesh *m, int form, const float *mu,
                           const float *lam, const float *dA, float *dx, float *dy,
                           float *dz, float *dmu, float *dlam,

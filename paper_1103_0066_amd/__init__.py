@@ -278,7 +278,7 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
                       coeff_grads: bool = True, counters: Optional[torch.Tensor] = None,
                       dmu: Optional[torch.Tensor] = None, dlam: Optional[torch.Tensor] = None,
                       store_rows: int = 0, deterministic: bool = False,
-                      no_alloc: bool = False):
+                      no_alloc: bool = False, precision: str = "fp32"):
     """Gradients of L = sum_e <dA_e, A_e>.
 
     Returns (dcoords [dim, N_v] float32, accumulated into ``dcoords`` when given,
@@ -288,7 +288,9 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
     ``no_alloc`` (with ``deterministic``) keeps that path's workspace in the
     library's fixed per-device array instead of allocating it
     (fei_integrate_adjoint_det_noalloc; at most FEI_NOALLOC_SCRATCH_BYTES of
-    workspace; calls that overlap on one device race)."""
+    workspace; calls that overlap on one device race).  ``precision`` other than
+    "fp32" folds dA into the geometric-tensor gradient on the matrix cores with
+    dA split into 16-bit terms (whole-matrix staging; FP32 coordinates)."""
     lib = _lib.load()
     m = _mesh(coords, conn)
     dev = coords.device
@@ -310,7 +312,7 @@ def integrate_adjoint(coords: torch.Tensor, conn: torch.Tensor, form: str, dA: t
         _require(dlam, "dlam", torch.float32, dev, (E,))
     else:
         dmu = dlam = None
-    o = _options("fp32", tau, counters, store_rows)
+    o = _options(precision, tau, counters, store_rows)
     if no_alloc and not deterministic:
         raise ValueError("no_alloc applies to the deterministic adjoint")
     entry = (lib.fei_integrate_adjoint_det_noalloc if no_alloc else

@@ -25,6 +25,17 @@
 // next chunk's loads are in flight while the lanes owning this chunk's
 // elements fold it, and no line is fetched twice.
 //
+// Split-precision MFMA fold (PREC = FP16x2, BF16x2, BF16x3; whole-matrix
+// staging): the fold of a staged chunk is the dense product
+//   U^T[g][elements] = Kf[g][ij] . dA^T[ij][elements]
+// on v_mfma_f32_16x16x32_{f16,bf16}, every lane of the wave taking part (16
+// elements per MFMA column block).  dA is split into two or three 16-bit
+// terms (FP16 with a power-of-two scale per element, undone exactly), each
+// multiplied by the same integer Kf, which is exact in both formats; the
+// products accumulate in FP32 and pass through LDS to the lane that owns the
+// element.  The reverse geometry stays FP32 (FP64 for flagged elements, whose
+// fold is FP64 as in the FP32 form).
+//
 // Elements flagged by the quality test run the reverse geometry in FP64, and
 // their U is recomputed in FP64 too: for such a tet (kappa ~ 1e3) the FP32
 // rounding of U alone is amplified to ~1e-4 in dL/dx.  That FP64 fold is done
@@ -33,12 +44,17 @@
 // FP64 coordinates run everything in FP64.
 #pragma once
 
-#include "fwd_fma.h"
+#include "fwd_mfma.h"
 
 namespace fei {
 
 template <int FORM, int DIM>
 __device__ KSparse<FORM, DIM> g_ksparse;
+
+// A fragments of the MFMA fold per (form, dim, 16-bit format); values
+// generated at build time.
+template <int FORM, int DIM, int PREC>
+__device__ AdjFragTable<FORM, DIM, PREC> g_adj_frags;
 
 // S accessors: from registers (U as accumulated) or from an LDS copy.
 template <int FORM, int DIM, typename AccT>
@@ -270,8 +286,9 @@ __device__ __forceinline__ void scatter_vertices(const AdjParams &p, const int (
 }
 
 // GATHER: the tile always writes J-bar (AdjParams.jbar) and carries no vertex
-// table; otherwise it scatters, or writes J-bar when jbar is set.
-template <int FORM, int DIM, typename CT, int R, bool GATHER = false>
+// table; otherwise it scatters, or writes J-bar when jbar is set.  PREC other
+// than P_FP32: the MFMA fold (whole-matrix staging, FP32 coordinates).
+template <int FORM, int DIM, typename CT, int R, bool GATHER = false, int PREC = P_FP32>
 struct AdjTile {
     using T = Traits<FORM, DIM>;
     using S = Stage<FORM, DIM, R>;
@@ -281,21 +298,35 @@ struct AdjTile {
     // Whole-matrix staging (R = n, n*n a multiple of 4): EC elements per
     // chunk, NWC chunks per wave, WP 16-byte pieces per chunk (WNP per lane).
     static constexpr bool WHOLE = (R == T::N) && (NN % 4 == 0);
-    static constexpr int EC = WHOLE ? ((64 * (NN + 4) * 4 <= 20 * 1024) ? 64 : 32) : 64;
+    static constexpr bool MF = PREC != P_FP32;
+    static_assert(!MF || (WHOLE && sizeof(CT) == 4), "MFMA fold: whole matrices, FP32 coordinates");
+    using MS = MfmaAdjShape<FORM, DIM>;
+    // MFMA fold: A fragments in registers when they take at most 32 VGPRs,
+    // else in LDS (one copy per workgroup); chunks of 16 matrices (one MFMA
+    // column block) when 64 would not fit 20 KB
+    static constexpr bool AFREG = MS::MT * MS::KS <= 8;
+    static constexpr int EC = WHOLE ? ((64 * (NN + 4) * 4 <= 20 * 1024) ? 64 : (MF ? 16 : 32)) : 64;
     static constexpr int NWC = WHOLE ? 64 / EC : 0;
     static constexpr int WP = EC * NN / 4;
     static constexpr int WNP = (WP + 63) / 64;
     // Next chunk in flight while this one is folded, where registers allow it
     // (the 12 x 12 matrices' 18 KB chunk would hold 72 more registers next to
     // U and the FP64 chain: the waves resident beside this one cover the
-    // latency instead).
-    static constexpr bool WPREFETCH = WNP * 4 + T::G <= 100;
+    // latency instead).  The MFMA fold holds its accumulators (16 per M
+    // tile) and the register-resident A fragments instead of U.
+    static constexpr bool WPREFETCH = MF
+        ? (8 * WNP + 16 * MS::MT + (AFREG ? 4 * MS::MT * MS::KS : 0) <= 140)
+        : (WNP * 4 + T::G <= 100);
     static constexpr int SLOTS = GATHER ? 0 : kHashSlots;
+    // U^T rows of the MFMA fold, transposed through LDS (row stride UST floats)
+    static constexpr int UST = 16 * MS::MT + 4;
     // A whole-matrix chunk buffer is reused, once the fold is done, for the
     // FP64 fold of flagged elements (dA row + GP doubles), the vertex-merge
-    // table and the J-bar staging; it must hold each of them.
-    static constexpr int WHOLE_SW = (EC * S::STR > 64 * DIM * DIM + 4)
+    // table, the J-bar staging and the MFMA fold's transpose; it must hold
+    // each of them.
+    static constexpr int WHOLE_SW0 = (EC * S::STR > 64 * DIM * DIM + 4)
         ? EC * S::STR : 64 * DIM * DIM + 4;
+    static constexpr int WHOLE_SW = (MF && 64 * UST > WHOLE_SW0) ? 64 * UST : WHOLE_SW0;
     static constexpr int WHOLE_SW2 = (WHOLE_SW > SLOTS * (1 + DIM)) ? WHOLE_SW : SLOTS * (1 + DIM);
     // (whole staging: the FP64 fold of a flagged element runs while its chunk
     // is staged, from the chunk, into GP doubles past the chunk buffer)
@@ -316,7 +347,8 @@ struct AdjTile {
     static constexpr int OFF_KEY = OFF_U64 + (WHOLE ? 0 : 4 * GP * 8);
     static constexpr int OFF_VAL = OFF_KEY + (WHOLE ? 0 : 4 * SLOTS * 4);
     static constexpr int OFF_STASH = OFF_VAL + (WHOLE ? 0 : 4 * SLOTS * DIM * 4);
-    static constexpr int LDS_BYTES = OFF_STASH + 4 * NSTASH * NN * 4;
+    static constexpr int OFF_FRAG = OFF_STASH + 4 * NSTASH * NN * 4;
+    static constexpr int LDS_BYTES = OFF_FRAG + ((MF && !AFREG) ? MS::NFRAG * 16 : 0);
 
     struct Lds {
         float *st;       // staging rows (SW floats)
@@ -350,6 +382,35 @@ struct AdjTile {
     struct Chunk {       // the wave's 16-byte dA pieces of one staged chunk
         f32x4_t r[WHOLE ? WNP : (R > 0) ? S::NV4 : 1];
     };
+    struct AFrags {      // MFMA fold: register-resident A fragments
+        uint4 v[(MF && AFREG) ? MS::MT * MS::KS : 1];
+    };
+    static constexpr int TP = (PREC == P_FP16X2) ? P_FP16X2 : P_BF16X2;   // fragment encoding
+
+    // A fragments into registers, or into LDS with a workgroup barrier; once
+    // per workgroup, before the first tile.
+    __device__ static void load_afrags(AFrags &a, unsigned char *smem)
+    {
+        if constexpr (MF) {
+            const uint4 *gfr = reinterpret_cast<const uint4 *>(g_adj_frags<FORM, DIM, TP>.v);
+            if constexpr (AFREG) {
+                const int lane = threadIdx.x & 63;
+#pragma unroll
+                for (int i = 0; i < MS::MT * MS::KS; ++i) a.v[i] = gfr[i * 64 + lane];
+            } else {
+                uint4 *sf = reinterpret_cast<uint4 *>(smem + OFF_FRAG);
+                for (int i = threadIdx.x; i < MS::NFRAG; i += 256) sf[i] = gfr[i];
+                __syncthreads();
+            }
+        }
+    }
+
+    __device__ static uint4 afrag(const AFrags &a, const unsigned char *smem, int t, int s)
+    {
+        if constexpr (AFREG) return a.v[t * MS::KS + s];
+        else return reinterpret_cast<const uint4 *>(smem + OFF_FRAG)[(t * MS::KS + s) * 64 +
+                                                                    (threadIdx.x & 63)];
+    }
 
     // Loads of lanes past the last element (and of tiles past the end) read
     // the last element; their results are never used.  No branch around a
@@ -494,6 +555,115 @@ struct AdjTile {
                 const float r[4] = {w[0], w[1], w[2], w[3]};
                 fold_piece<FORM, DIM, AccT>(U, k, r, 4);
             }
+        }
+    }
+
+    // MFMA fold of staged chunk c (EC elements, EC / 16 column blocks): lane
+    // (n, q) = (lane % 16, lane / 16) takes entries 32 s + 8 q .. + 8 of
+    // element n of a block, splits them and multiplies them with the A
+    // fragments; acc[b][t] then holds U^T rows 16 t + 4 q .. + 4 of the wave's
+    // element 16 b + n.
+    __device__ static void mfma_fold(const Lds &L, int c, const AFrags &af,
+                                     const unsigned char *smem, floatx4_t (&acc)[4][MS::MT])
+    {
+        if constexpr (MF) {
+            const int lane = threadIdx.x & 63, n = lane & 15, q = lane >> 4;
+#pragma unroll
+            for (int bl = 0; bl < EC / 16; ++bl) {
+                const int b = c * (EC / 16) + bl;
+                const float *row = L.st + (bl * 16 + n) * S::STR;
+                float x[MS::KS][8];
+#pragma unroll
+                for (int s = 0; s < MS::KS; ++s)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int k0 = 32 * s + 8 * q + 4 * h;    // n*n is a multiple of 4
+                        f32x4_t w = {0.f, 0.f, 0.f, 0.f};
+                        if (k0 < NN) w = *reinterpret_cast<const f32x4_t *>(row + k0);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) x[s][4 * h + i] = w[i];
+                    }
+                int E = 0;
+                if constexpr (PREC == P_FP16X2) {
+                    // the element's scale: its 4 lanes (q = 0..3) hold all its entries
+                    float mx = 0.f;
+#pragma unroll
+                    for (int s = 0; s < MS::KS; ++s)
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) mx = fmaxf(mx, fabsf(x[s][j]));
+                    mx = fmaxf(mx, __shfl_xor(mx, 16));
+                    mx = fmaxf(mx, __shfl_xor(mx, 32));
+                    (void)frexpf(mx, &E);
+                    if (!(mx < __builtin_huge_valf())) E = 0;  // Inf / NaN: leave unscaled
+                }
+#pragma unroll
+                for (int s = 0; s < MS::KS; ++s) {
+                    uint16_t hv[8], lv[8], l2[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        if constexpr (PREC == P_FP16X2) {
+                            const float v = ldexpf(x[s][j], -E);
+                            const _Float16 hi = (_Float16)v;
+                            hv[j] = f16_bits(hi);
+                            lv[j] = f16_bits((_Float16)(v - (float)hi));
+                        } else {
+                            const float v = x[s][j];
+                            const __bf16 hi = (__bf16)v;
+                            const float r1 = v - (float)hi;
+                            const __bf16 mid = (__bf16)r1;
+                            hv[j] = bf16_bits(hi);
+                            lv[j] = bf16_bits(mid);
+                            l2[j] = bf16_bits((__bf16)(r1 - (float)mid));
+                        }
+                    }
+                    auto pack = [](const uint16_t (&h)[8]) {
+                        uint4 w;
+                        w.x = unsigned(h[0]) | (unsigned(h[1]) << 16);
+                        w.y = unsigned(h[2]) | (unsigned(h[3]) << 16);
+                        w.z = unsigned(h[4]) | (unsigned(h[5]) << 16);
+                        w.w = unsigned(h[6]) | (unsigned(h[7]) << 16);
+                        return w;
+                    };
+                    const uint4 bh = pack(hv), blo = pack(lv);
+#pragma unroll
+                    for (int t = 0; t < MS::MT; ++t) {
+                        const uint4 a = afrag(af, smem, t, s);
+                        acc[b][t] = mfma_step<PREC>(a, bh, acc[b][t]);
+                        acc[b][t] = mfma_step<PREC>(a, blo, acc[b][t]);
+                        if constexpr (PREC == P_BF16X3) acc[b][t] = mfma_step<PREC>(a, pack(l2), acc[b][t]);
+                    }
+                }
+                if constexpr (PREC == P_FP16X2) {
+#pragma unroll
+                    for (int t = 0; t < MS::MT; ++t)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) acc[b][t][i] = ldexpf(acc[b][t][i], E);
+                }
+            }
+        }
+    }
+
+    // The MFMA fold's accumulators to U of the owning lanes, through LDS.
+    __device__ static void mfma_unfold(const Lds &L, const floatx4_t (&acc)[4][MS::MT],
+                                       AccT (&U)[T::G])
+    {
+        if constexpr (MF) {
+            const int lane = threadIdx.x & 63, n = lane & 15, q = lane >> 4;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int t = 0; t < MS::MT; ++t)
+                    *reinterpret_cast<floatx4_t *>(L.st + (16 * b + n) * UST + 16 * t + 4 * q) =
+                        acc[b][t];
+            wave_sync();
+#pragma unroll
+            for (int g = 0; g < T::G; g += 4) {
+                const floatx4_t w = *reinterpret_cast<const floatx4_t *>(L.st + lane * UST + g);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (g + i < T::G) U[g + i] = w[i];
+            }
+            wave_sync();
         }
     }
 
@@ -647,6 +817,13 @@ struct AdjTile {
     // is folded, and chunk 0 travels with the connectivity and coordinates.
     __device__ __forceinline__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem)
     {
+        static_assert(!MF, "the MFMA fold takes its A fragments");
+        run(p, blk, smem, AFrags{});
+    }
+
+    __device__ __forceinline__ static void run(const AdjParams &p, int64_t blk, unsigned char *smem,
+                                               const AFrags &af)
+    {
         const Lds L = lds(smem);
         if constexpr (WHOLE) {
             // coordinates first (their loads complete before dA's), then the
@@ -667,13 +844,21 @@ struct AdjTile {
             AccT U[T::G];
 #pragma unroll
             for (int k = 0; k < T::G; ++k) U[k] = AccT(0);
+            floatx4_t acc[4][MS::MT];
+            if constexpr (MF) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int t = 0; t < MS::MT; ++t) acc[b][t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
             for (int c = 0; c < NWC; ++c) {
                 if (!WPREFETCH && c > 0) ch = load_whole(p, blk, c);
                 stage_whole(L, ch);
                 if (WPREFETCH && c + 1 < NWC) ch = load_whole(p, blk, c + 1);
                 wave_sync();
-                fold_whole(L, c, U);
+                if constexpr (MF) mfma_fold(L, c, af, smem, acc);
+                else fold_whole(L, c, U);
                 // flagged elements of this chunk among the wave's first NS64
                 unsigned long long fc = fm;
                 for (int sl = 0; sl < NS64 && fc; ++sl) {
@@ -683,6 +868,7 @@ struct AdjTile {
                 }
                 wave_sync();
             }
+            if constexpr (MF) mfma_unfold(L, acc, U);
             if constexpr (sizeof(CT) == 8) {
                 o = reverse(p, blk, g, U, 0ull, L);
             } else {
@@ -786,6 +972,19 @@ __global__ __launch_bounds__(256) void adj_fma_kernel(AdjParams p, int64_t n_til
             t = tn;
         }
     }
+}
+
+// MFMA fold (split precision): persistent grid, tiles split per XCD; the A
+// fragments are loaded once per workgroup.  Scatter or, with GATHER, J-bar.
+template <int FORM, int DIM, int PREC, bool GATHER>
+__global__ __launch_bounds__(256, 2) void adj_mfma_kernel(AdjParams p, int64_t n_tiles)
+{
+    using Tile = AdjTile<FORM, DIM, float, Traits<FORM, DIM>::N, GATHER, PREC>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[Tile::LDS_BYTES];
+    typename Tile::AFrags af;
+    Tile::load_afrags(af, smem);
+    const PersistentTiles pt(n_tiles);
+    for (int64_t t = pt.begin; t < pt.end; t += pt.stride) Tile::run(p, t, smem, af);
 }
 
 // The gather form (no vertex table: 59 KB of LDS and under 200 registers for

@@ -138,8 +138,8 @@ int prepare_adjoint(const fei_mesh *m, int form, const float *mu, const float *l
     if (!valid_form(form)) return fail(FEI_EINVAL, "unknown form %d", form);
     fei_options o = opt ? *opt : defaults();
     if ((rc = check_options(o))) return rc;
-    if (o.precision != FEI_PREC_FP32)
-        return fail(FEI_EUNSUPPORTED, "the adjoint is FP32 only");
+    if (o.precision != FEI_PREC_FP32 && m->coord_dtype != FEI_F32)
+        return fail(FEI_EUNSUPPORTED, "the split-precision adjoint takes FP32 coordinates");
     if ((rc = check_coeffs(form, mu, lam, m->n_elements))) return rc;
     if (form != FEI_ELASTIC_P1 && (dmu || dlam))
         return fail(FEI_EINVAL, "dmu/dlam must be NULL for a Laplacian form");

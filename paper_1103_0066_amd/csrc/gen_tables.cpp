@@ -80,6 +80,40 @@ static void emit_frags()
     std::printf("}};\n");
 }
 
+// A fragments of the adjoint's MFMA fold (the transpose of the forward's
+// operand, without the split stacking).
+template <int F, int D, int P>
+static void emit_adj_frags()
+{
+    using T = Traits<F, D>;
+    using S = MfmaAdjShape<F, D>;
+    std::printf("template <> __device__ AdjFragTable<%d, %d, %d> g_adj_frags<%d, %d, %d> = {{",
+                F, D, P, F, D, P);
+    int n = 0;
+    for (int t = 0; t < S::MT; ++t)
+        for (int s = 0; s < S::KS; ++s)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int m = 16 * t + lane % 16;
+                    const int k = 32 * s + 8 * (lane / 16) + j;
+                    int val = 0;
+                    if (m < T::G && k < S::NN) {
+                        int p = 0, q = 0;
+                        sym_pair(T::GD, m, p, q);
+                        val = kfolded(F, D, p, q, k / T::N, k % T::N);
+                    }
+                    if ((P == P_FP16X2 && (val > 2048 || val < -2048)) ||
+                        (P != P_FP16X2 && (val > 256 || val < -256))) {
+                        std::fprintf(stderr, "K entry %d not exact in 16 bits\n", val);
+                        std::exit(1);
+                    }
+                    const unsigned bits =
+                        (P == P_FP16X2) ? f16_bits_of_int(val) : bf16_bits_of_int(val);
+                    std::printf("%s0x%04x", sep(n++), bits);
+                }
+    std::printf("}};\n");
+}
+
 template <int F, int D>
 static void emit_sparse()
 {
@@ -124,6 +158,8 @@ static void emit_form()
     emit_frags<F, D, P_FP16X2>();
     emit_frags<F, D, P_BF16X2>();
     emit_frags<F, D, P_BF16X3>();
+    emit_adj_frags<F, D, P_FP16X2>();
+    emit_adj_frags<F, D, P_BF16X2>();
 }
 
 // Isoparametric P2 Laplacian: K^{ijkl}_{mu nu} = int_ref lambda_k dphi_i/dxi_mu

@@ -92,6 +92,33 @@ hipError_t launch_adj_fma(const AdjParams &p, hipStream_t s)
     }
 }
 
+template <int F, int D, int PREC, bool GATHER>
+hipError_t launch_adj_mfma(const AdjParams &p, hipStream_t s)
+{
+    return launch_persistent<adj_mfma_kernel<F, D, PREC, GATHER>>(p, s);
+}
+
+// Split-precision adjoint: the MFMA fold over whole staged matrices (n*n a
+// multiple of 4: every form but the 3 x 3 matrices of the 2D P1 Laplacian),
+// FP32 coordinates.
+template <int F, int D>
+AdjLauncher adj_mfma_for(const Variant &v)
+{
+    constexpr int N = Traits<F, D>::N;
+    if constexpr ((N * N) % 4 != 0) {
+        return nullptr;
+    } else {
+        if (v.coord_f64 || (v.rows != 0 && v.rows != N)) return nullptr;
+        const bool g = v.gather != 0;
+        switch (v.precision) {
+        case P_FP16X2: return g ? &launch_adj_mfma<F, D, P_FP16X2, true> : &launch_adj_mfma<F, D, P_FP16X2, false>;
+        case P_BF16X2: return g ? &launch_adj_mfma<F, D, P_BF16X2, true> : &launch_adj_mfma<F, D, P_BF16X2, false>;
+        case P_BF16X3: return g ? &launch_adj_mfma<F, D, P_BF16X3, true> : &launch_adj_mfma<F, D, P_BF16X3, false>;
+        default: return nullptr;
+        }
+    }
+}
+
 // Staging rows R that fit: R divides n, R*n floats is a whole number of
 // 16-byte pieces, and four waves' staging buffers fit in the 160 KB LDS.
 template <int F, int D, int R>
@@ -245,7 +272,7 @@ FwdLauncher fwd_for_coords(const Variant &v)
 template <int F, int D>
 AdjLauncher adj_for_coords(const Variant &v)
 {
-    if (v.precision != P_FP32) return nullptr;
+    if (v.precision != P_FP32) return adj_mfma_for<F, D>(v);
     if (v.gather) {   // plans' vertex gather: FP32 coordinates, default staging
         if (v.coord_f64 || v.rows != 0) return nullptr;
         return &launch_adj_fma<F, D, float, default_gather_rows<F, D>(), true>;

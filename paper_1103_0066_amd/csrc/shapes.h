@@ -23,6 +23,19 @@ struct MfmaShape {
     static constexpr int BROW = KT + 8;                          // LDS row (halfs), padded
 };
 
+// MFMA form of the adjoint's fold U^T[g][elements] = Kf[g][ij] dA^T[ij][elements]
+// with 16x16x32 tiles: M = unique pairs g (MT tiles), K = element-matrix
+// entries ij (KS steps of 32).  The split terms of dA are separate products
+// with the same A fragments.
+template <int FORM, int DIM>
+struct MfmaAdjShape {
+    using T = Traits<FORM, DIM>;
+    static constexpr int NN = T::N * T::N;
+    static constexpr int MT = (T::G + 15) / 16;
+    static constexpr int KS = (NN + 31) / 32;
+    static constexpr int NFRAG = MT * KS * 64;
+};
+
 // Block reference tensor [NB][NB][DIM][DIM] (integer values, as float).
 template <int FORM, int DIM>
 struct KBlockTable {
@@ -35,6 +48,15 @@ struct KBlockTable {
 template <int FORM, int DIM, int PREC>
 struct FragTable {
     uint16_t v[MfmaShape<FORM, DIM, PREC>::NFRAG * 8];
+};
+
+// Adjoint fragments in lane order: fragment f = (t*KS + s)*64 + lane holds
+// A[m][32 s + 8 (lane/16) + j], j = 0..7, with m = 16 t + lane % 16 and
+// A[m][ij] = Kf[m][ij] for m < G and ij < n*n, else 0.  PREC is P_FP16X2 or
+// P_BF16X2 (the encoding; BF16x3 uses the BF16 table).
+template <int FORM, int DIM, int PREC>
+struct AdjFragTable {
+    uint16_t v[MfmaAdjShape<FORM, DIM>::NFRAG * 8];
 };
 
 // Sparse rows of the folded tensor: for every unique pair g the nonzero

@@ -210,13 +210,21 @@ def test_empty_mesh_is_a_noop():
     assert rc == 0
 
 
-def test_adjoint_is_fp32_only():
+def test_split_precision_adjoint_rejections():
+    """Split-precision adjoints need FP32 coordinates, whole-matrix staging and
+    n*n a multiple of 4: every other variant is refused before any launch."""
     lib = _lib.load()
-    m = _fake_mesh()
-    o = _opts(precision=1)
-    rc = lib.fei_integrate_adjoint(ctypes.byref(m), 1, None, None, FAKE, FAKE, FAKE, FAKE,
-                                   None, None, ctypes.byref(o), None)
-    assert rc == _lib.FEI_EUNSUPPORTED
+    for prec in (1, 2, 3):
+        cases = [(_fake_mesh(dtype=_lib.F64), 1, _opts(precision=prec)),     # FP64 coordinates
+                 (_fake_mesh(dim=2), 1, _opts(precision=prec)),              # 3 x 3 matrices
+                 (_fake_mesh(), 2, _opts(precision=prec, store_rows=2)),     # row chunks
+                 (_fake_mesh(), 3, _opts(precision=prec, store_rows=-1))]    # direct reads
+        for m, form, o in cases:
+            coef = FAKE if form == 2 else None
+            rc = lib.fei_integrate_adjoint(ctypes.byref(m), form, coef, coef, FAKE, FAKE, FAKE,
+                                           FAKE if m.dim == 3 else None, None, None,
+                                           ctypes.byref(o), None)
+            assert rc == _lib.FEI_EUNSUPPORTED, (prec, form, m.dim, m.coord_dtype)
 
 
 def test_adjoint_rejects_coefficient_grads_for_laplace():
