@@ -521,7 +521,15 @@ def main():
         c, cn, mu, lam = sets[k]
         return lambda: fei.integrate(c, cn, "elastic_p1", mu, lam, precision=prec, out=outs[k])
 
-    # ---- headline: plain FP32 forward -------------------------------------
+    # ---- headline: plain FP32 forward, launch shape from the tuner ---------
+    # (fei_tune_forward times the elements-per-workgroup and staging
+    # candidates on this mesh and records the fastest; the timed calls below
+    # take it from the tune table)
+    c0, cn0, mu0, lam0 = sets[0]
+    tuned = fei.tune_forward(c0, cn0, "elastic_p1", mu0, lam0, out=outs[0])
+    progress(f"tuned launch shape of the headline forward: {tuned}")
+    blk = tuned["block_elements"] or 256            # 0 in the table: the built-in default
+    rows = tuned["store_rows"] or 12
     head = time_leg([fwd("fp32", k) for k in range(S)], args.steps, args.warmup, "fp32")
     ms = head["wall_ms_per_step"]
     achieved = fwd_bytes / (head["kernel_ms_mean"] * 1e-3) / 1e9
@@ -541,11 +549,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name.replace("adjoint of ", ""), "elements": E,
                    "vertices": Nv, "precision": "fp32", "tau": 100.0,
-                   "algorithmic_bytes_per_step": fwd_bytes, "buffer_sets": S},
+                   "algorithmic_bytes_per_step": fwd_bytes, "buffer_sets": S,
+                   "tuned_launch": {"block_elements": blk, "store_rows": rows}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": head_traffic,
-                     "kernel": "fwd_fma_kernel<elastic_p1, 3, float, 12>",
+                     "kernel": f"fwd_fma_kernel<elastic_p1, 3, float, {rows}, {blk // 64}>",
                      "kernel_ms_mean": head["kernel_ms_mean"],
                      "algorithmic_bytes_per_launch": fwd_bytes},
     }
@@ -573,7 +582,8 @@ def main():
     # ---- adjoint of the same workload ------------------------------------------
     ab = adjoint_bytes(E, Nv, 12, 3, True)
     if any(want(args, k, "adjoint") for k in ("adjoint_fp32", "adjoint_det_fp32",
-                                              "adjoint_plan_fp32")):
+                                              "adjoint_plan_fp32", "adjoint_fp16x2",
+                                              "adjoint_bf16x2", "adjoint_bf16x3")):
         A_plan = outs[0]            # the plans' forward output (their forward is not run)
         del outs
         torch.cuda.empty_cache()
@@ -582,11 +592,11 @@ def main():
         dmus = [torch.empty(E, dtype=torch.float32, device=dev) for _ in range(S)]
         dlams = [torch.empty(E, dtype=torch.float32, device=dev) for _ in range(S)]
 
-        def adj(k, det=False):
+        def adj(k, det=False, prec="fp32"):
             c, cn, mu, lam = sets[k]
             return lambda: fei.integrate_adjoint(c, cn, "elastic_p1", dAs[k], mu, lam,
                                                  dcoords=dcs[k], dmu=dmus[k], dlam=dlams[k],
-                                                 deterministic=det)
+                                                 deterministic=det, precision=prec)
 
         def adj_acc(name, run):
             if args.no_accuracy:
@@ -604,6 +614,19 @@ def main():
             legs["adjoint_fp32"] = rates(r, ab, E, 0, copy_gbs,
                                          stored_traffic("elastic_p1_3d_adjoint_fp32"))
             adj_acc("adjoint_fp32", adj(0))
+        for prec in ("fp16x2", "bf16x2", "bf16x3"):
+            name = f"adjoint_{prec}"
+            if not want(args, name, "adjoint"):
+                continue
+            r = time_leg([adj(k, prec=prec) for k in range(S)], args.steps, args.warmup, name)
+            legs[name] = rates(r, ab, E, 0, copy_gbs,
+                               stored_traffic(f"elastic_p1_3d_adjoint_{prec}"))
+            legs[name]["note"] = ("the fold of dA with K on the matrix cores, dA split into "
+                                  "16-bit terms; whole-matrix staging; atomic vertex scatter")
+            if "adjoint_fp32" in legs:
+                legs[name]["speedup_vs_fp32"] = (legs["adjoint_fp32"]["kernel_ms_mean"]
+                                                 / legs[name]["kernel_ms_mean"])
+            adj_acc(name, adj(0, prec=prec))
         if want(args, "adjoint_det_fp32", "adjoint"):
             r = time_leg([adj(k, True) for k in range(S)], args.steps, args.warmup,
                          "adjoint_det_fp32")

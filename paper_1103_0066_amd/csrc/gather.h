@@ -21,21 +21,76 @@ __global__ __launch_bounds__(256) void incidence_zero_kernel(int32_t *a, int64_t
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += gridDim.x * 256ll) a[i] = 0;
 }
 
-// deg[v + 1] = number of incidences of v (ptr[0] stays 0).
+// Count and fill take the references in batches of kIncBatch per workgroup
+// and first merge them per vertex in an LDS open-addressing table (CAS on the
+// key, LDS atomics on the count): on a mesh with locality a batch names far
+// fewer distinct vertices than references (about a fifth for consecutive Kuhn
+// tets), and global atomics, which execute at the memory side, are the cost.
+// The table has twice as many slots as a batch has references, so it never
+// fills and every probe sequence ends.
+constexpr int kIncBatch = 1024;
+constexpr int kIncSlots = 2 * kIncBatch;
+
+__device__ __forceinline__ int inc_slot(int32_t v)
+{
+    return int((unsigned(v) * 2654435761u) >> (32 - 11));   // 11 bits: kIncSlots
+}
+
+// Inserts v into the table; returns its slot.
+__device__ __forceinline__ int inc_insert(int32_t *key, int32_t v)
+{
+    int h = inc_slot(v);
+    for (int probe = 0; probe < kIncSlots; ++probe) {
+        const int32_t old = atomicCAS(key + h, -1, v);
+        if (old == -1 || old == v) break;
+        h = (h + 1) & (kIncSlots - 1);
+    }
+    return h;
+}
+
+__device__ __forceinline__ void inc_clear(int32_t *key, int32_t *cnt)
+{
+    for (int i = threadIdx.x; i < kIncSlots; i += 256) {
+        key[i] = -1;
+        cnt[i] = 0;
+    }
+}
+
+// deg[v + 1] = number of incidences of v (ptr[0] stays 0; ptr zeroed before).
 __global__ __launch_bounds__(256) void incidence_count_kernel(Incidence g)
 {
+    __shared__ int32_t key[kIncSlots];
+    __shared__ int32_t cnt[kIncSlots];
     const int64_t total = g.n_elements * g.nv;
-    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += gridDim.x * 256ll) {
-        const int32_t v = g.conn[i];
-        if (v >= 0 && v < g.n_vertices) atomicAdd(g.ptr + v + 1, 1);
+    inc_clear(key, cnt);
+    __syncthreads();
+    for (int64_t base = blockIdx.x * int64_t(kIncBatch); base < total;
+         base += gridDim.x * int64_t(kIncBatch)) {
+#pragma unroll
+        for (int k = 0; k < kIncBatch / 256; ++k) {
+            const int64_t i = base + threadIdx.x + 256 * k;
+            if (i < total) {
+                const int32_t v = g.conn[i];
+                if (v >= 0 && v < g.n_vertices) atomicAdd(cnt + inc_insert(key, v), 1);
+            }
+        }
+        __syncthreads();
+        for (int sl = threadIdx.x; sl < kIncSlots; sl += 256) {
+            const int32_t v = key[sl];
+            if (v >= 0) atomicAdd(g.ptr + v + 1, cnt[sl]);
+        }
+        __syncthreads();
+        inc_clear(key, cnt);
+        __syncthreads();
     }
 }
 
 // In-place inclusive scan of ptr[0 .. n) by one workgroup: each thread scans a
 // contiguous chunk, the chunk totals are scanned in LDS, then added back.
 // The chunk loops read 16 values per step into registers before using any,
-// so a thread waits for one memory latency per 16 values, not per value
-// (290K vertices: 541 -> ~40 us).
+// so a thread waits for one memory latency per 16 values, not per value.
+// Used for short arrays (up to one block of the multi-block scan below, and
+// that scan's block totals).
 constexpr int kScanBatch = 16;
 __global__ __launch_bounds__(1024) void incidence_scan_kernel(int32_t *ptr, int64_t n)
 {
@@ -79,15 +134,101 @@ __global__ __launch_bounds__(1024) void incidence_scan_kernel(int32_t *ptr, int6
     }
 }
 
+// Multi-block inclusive scan of ptr[0 .. n): each workgroup scans its
+// kScanBlock entries (loaded and stored coalesced through LDS, 16 contiguous
+// values per thread, one padding word per 16 so the per-thread runs fall in
+// different banks) and writes its total to sums[block]; the totals are
+// scanned by incidence_scan_kernel and added back by incidence_add_kernel.
+constexpr int kScanBlock = 16 * 256;
+__global__ __launch_bounds__(256) void incidence_scan_blocks_kernel(int32_t *ptr, int64_t n,
+                                                                    int32_t *sums)
+{
+    __shared__ int32_t buf[kScanBlock + kScanBlock / 16];
+    __shared__ int32_t tot[256];
+    const int t = threadIdx.x;
+    const int64_t b0 = blockIdx.x * int64_t(kScanBlock);
+    auto pad = [](int j) { return j + (j >> 4); };
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int j = k * 256 + t;
+        buf[pad(j)] = (b0 + j < n) ? ptr[b0 + j] : 0;
+    }
+    __syncthreads();
+    int32_t v[16];
+    int32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        run += buf[pad(16 * t + k)];
+        v[k] = run;
+    }
+    tot[t] = run;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t x = t >= off ? tot[t - off] : 0;
+        __syncthreads();
+        tot[t] += x;
+        __syncthreads();
+    }
+    const int32_t pre = t > 0 ? tot[t - 1] : 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) buf[pad(16 * t + k)] = v[k] + pre;
+    if (t == 255) sums[blockIdx.x] = tot[255];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int j = k * 256 + t;
+        if (b0 + j < n) ptr[b0 + j] = buf[pad(j)];
+    }
+}
+
+__global__ __launch_bounds__(256) void incidence_add_kernel(int32_t *ptr, int64_t n,
+                                                            const int32_t *sums)
+{
+    const int64_t blk = blockIdx.x + 1;           // block 0 has no offset
+    const int32_t off = sums[blk - 1];
+    const int64_t b0 = blk * int64_t(kScanBlock);
+    for (int j = threadIdx.x; j < kScanBlock; j += 256)
+        if (b0 + j < n) ptr[b0 + j] += off;
+}
+
+// inc[ptr[v] + slot] = e * nv + a for every reference; the slots of one
+// vertex are reserved per batch with one global atomic and handed out by LDS
+// atomics, so their order is arbitrary until the sort.
 __global__ __launch_bounds__(256) void incidence_fill_kernel(Incidence g)
 {
+    __shared__ int32_t key[kIncSlots];
+    __shared__ int32_t cnt[kIncSlots];       // batch count, then the batch's base in the list
     const int64_t total = g.n_elements * g.nv;
-    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += gridDim.x * 256ll) {
-        const int32_t v = g.conn[i];
-        if (v >= 0 && v < g.n_vertices) {
-            const int32_t pos = atomicAdd(g.cursor + v, 1);
-            g.inc[g.ptr[v] + pos] = int32_t(i);   // i = e * nv + a
+    inc_clear(key, cnt);
+    __syncthreads();
+    for (int64_t base = blockIdx.x * int64_t(kIncBatch); base < total;
+         base += gridDim.x * int64_t(kIncBatch)) {
+        int slot[kIncBatch / 256], rank[kIncBatch / 256];
+#pragma unroll
+        for (int k = 0; k < kIncBatch / 256; ++k) {
+            const int64_t i = base + threadIdx.x + 256 * k;
+            slot[k] = -1;
+            rank[k] = 0;
+            if (i < total) {
+                const int32_t v = g.conn[i];
+                if (v >= 0 && v < g.n_vertices) {
+                    slot[k] = inc_insert(key, v);
+                    rank[k] = atomicAdd(cnt + slot[k], 1);
+                }
+            }
         }
+        __syncthreads();
+        for (int sl = threadIdx.x; sl < kIncSlots; sl += 256) {
+            const int32_t v = key[sl];
+            if (v >= 0) cnt[sl] = g.ptr[v] + atomicAdd(g.cursor + v, cnt[sl]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kIncBatch / 256; ++k)
+            if (slot[k] >= 0) g.inc[cnt[slot[k]] + rank[k]] = int32_t(base + threadIdx.x + 256 * k);
+        __syncthreads();
+        inc_clear(key, cnt);
+        __syncthreads();
     }
 }
 
@@ -115,24 +256,38 @@ __device__ inline void heap_sort(int32_t *a, int32_t n)
     }
 }
 
-// Sorts every vertex's incidences: insertion sort for the usual short lists
-// (~24 per vertex on meshes of tets), heapsort beyond 32.
+// Sorts every vertex's incidences.  A wave takes kSortVerts consecutive
+// vertices: their lists (up to 64 entries each, one per lane) are loaded
+// together, each entry's rank is the number of smaller entries of its list
+// (the entries are distinct), and every entry is stored at its rank.  Longer
+// lists (vertices of degree above 64) are heap-sorted by one lane.
+constexpr int kSortVerts = 8;
 __global__ __launch_bounds__(256) void incidence_sort_kernel(Incidence g)
 {
-    for (int64_t v = blockIdx.x * 256ll + threadIdx.x; v < g.n_vertices; v += gridDim.x * 256ll) {
-        const int32_t b = g.ptr[v], e = g.ptr[v + 1];
-        if (e - b > 32) {
-            heap_sort(g.inc + b, e - b);
-            continue;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * 256ll + threadIdx.x) >> 6;
+    const int64_t n_waves = (int64_t(gridDim.x) * 256) >> 6;
+    for (int64_t v0 = wave * kSortVerts; v0 < g.n_vertices; v0 += n_waves * kSortVerts) {
+        int32_t b[kSortVerts + 1];
+#pragma unroll
+        for (int j = 0; j <= kSortVerts; ++j)
+            b[j] = g.ptr[v0 + j < g.n_vertices ? v0 + j : g.n_vertices];
+        int32_t x[kSortVerts];
+#pragma unroll
+        for (int j = 0; j < kSortVerts; ++j) {
+            const int32_t L = b[j + 1] - b[j];
+            x[j] = (L <= 64 && lane < L) ? g.inc[b[j] + lane] : 0;
         }
-        for (int32_t i = b + 1; i < e; ++i) {
-            const int32_t x = g.inc[i];
-            int32_t j = i - 1;
-            while (j >= b && g.inc[j] > x) {
-                g.inc[j + 1] = g.inc[j];
-                --j;
+#pragma unroll
+        for (int j = 0; j < kSortVerts; ++j) {
+            const int32_t L = b[j + 1] - b[j];
+            if (L <= 64) {
+                int32_t r = 0;
+                for (int32_t k = 0; k < L; ++k) r += __builtin_amdgcn_readlane(x[j], k) < x[j];
+                if (lane < L) g.inc[b[j] + r] = x[j];
+            } else if (lane == 0) {
+                heap_sort(g.inc + b[j], L);
             }
-            g.inc[j + 1] = x;
         }
     }
 }

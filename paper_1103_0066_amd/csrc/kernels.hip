@@ -502,10 +502,30 @@ hipError_t launch_incidence_build(const Incidence &g, hipStream_t s)
                        g.n_vertices + 1);
     hipLaunchKernelGGL(incidence_zero_kernel, dim3(grid(g.n_vertices)), dim3(256), 0, s, g.cursor,
                        g.n_vertices);
-    hipLaunchKernelGGL(incidence_count_kernel, dim3(grid(total)), dim3(256), 0, s, g);
-    hipLaunchKernelGGL(incidence_scan_kernel, dim3(1), dim3(1024), 0, s, g.ptr, g.n_vertices + 1);
-    hipLaunchKernelGGL(incidence_fill_kernel, dim3(grid(total)), dim3(256), 0, s, g);
-    hipLaunchKernelGGL(incidence_sort_kernel, dim3(grid(g.n_vertices)), dim3(256), 0, s, g);
+    // count and fill: one batch of kIncBatch references per workgroup step
+    const unsigned gb = unsigned(std::min<int64_t>((total + kIncBatch - 1) / kIncBatch, 4096));
+    if (gb > 0) hipLaunchKernelGGL(incidence_count_kernel, dim3(gb), dim3(256), 0, s, g);
+    // scan of ptr[0 .. n_vertices]: one workgroup for a single block, else
+    // block scans, a scan of their totals (kept in cursor, which is zeroed
+    // again before the fill) and the offsets added back
+    const int64_t n = g.n_vertices + 1;
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb <= 1) {
+        hipLaunchKernelGGL(incidence_scan_kernel, dim3(1), dim3(1024), 0, s, g.ptr, n);
+    } else {
+        // nb <= n_vertices here: cursor [n_vertices] holds the block totals
+        hipLaunchKernelGGL(incidence_scan_blocks_kernel, dim3(unsigned(nb)), dim3(256), 0, s, g.ptr,
+                           n, g.cursor);
+        hipLaunchKernelGGL(incidence_scan_kernel, dim3(1), dim3(1024), 0, s, g.cursor, nb);
+        hipLaunchKernelGGL(incidence_add_kernel, dim3(unsigned(nb - 1)), dim3(256), 0, s, g.ptr, n,
+                           g.cursor);
+        hipLaunchKernelGGL(incidence_zero_kernel, dim3(grid(nb)), dim3(256), 0, s, g.cursor, nb);
+    }
+    if (gb > 0) hipLaunchKernelGGL(incidence_fill_kernel, dim3(gb), dim3(256), 0, s, g);
+    const int64_t sw = (g.n_vertices + kSortVerts - 1) / kSortVerts;     // waves of the sort
+    if (sw > 0)
+        hipLaunchKernelGGL(incidence_sort_kernel, dim3(unsigned(std::min<int64_t>((sw + 3) / 4, 8192))),
+                           dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
