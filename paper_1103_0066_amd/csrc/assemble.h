@@ -5,33 +5,35 @@
 // portion of the computation that element integration feeds (Sec. 1), with
 // the local portion, A_e = G_e : K (Sec. 3, eq. 1), computed on the fly.
 //
-// Rows are gathered, not scattered: one wave owns a contiguous range of rows
-// (a host-built chunk whose blocks fit the wave's LDS accumulator) and walks
-// their vertex-to-element incidences, 64 at a time, one lane per incidence
-// (e, a).  The lane recomputes element e's geometric tensor (eq. 8 or its
-// Lame analogue, FP64 for flagged elements, exactly as the forward), forms
-// row block a of A_e and adds its n / NC blocks into the row's slots in LDS;
-// the slot of column vertex conn[e][b] is found by binary search in the row's
-// sorted column list.  No other wave touches the rows, so the sums need no
-// global atomics, and the adds of a wave execute in program order (one LDS
-// atomic instruction per block entry and local vertex b).  The finished rows
-// leave as one contiguous run of values.
+// Rows are gathered, not scattered, and every row has owners: a wave takes a
+// contiguous range of up to kAsmRows rows (a host-built chunk whose blocks
+// fit the wave's LDS accumulator), and the kAsmLanes lanes r, r + kAsmRows, ..
+// own row r of it.  They walk the row's vertex-to-element incidences (e, a),
+// lane k of the row taking incidences k, k + kAsmLanes, .., recomputing
+// element e's geometric tensor (eq. 8 or its Lame
+// analogue, FP64 for flagged elements, exactly as the forward), forming row
+// block a of A_e and adding its n / NC blocks into the row's slots in LDS; the
+// slot of column vertex conn[e][b] is found by binary search in the row's
+// sorted column list.  The lanes of one part of the wave own distinct rows,
+// so their adds touch distinct slots: the parts add in turn with plain LDS
+// read-modify-writes, no atomics (LDS float atomics, where the lanes of a row
+// collide on its slots, measured 6x slower), and every sum runs in the order
+// of the row's incidence list, so every run gives the same bits.  The
+// finished rows leave as one contiguous run of values.
 //
-// For P1 the reference tensor factors, K^{ab}_{mu nu} = g_a,mu g_b,nu (eq. 7
-// with constant barycentric gradients g), so row block a is
-//   w[nu][c][d]     = sum_mu g_a,mu T^{(mu c),(nu d)}
-//   A_{(a,c),(b,d)} = sum_nu g_b,nu w[nu][c][d],
-// where the runtime a selects among the compile-time rows of T (g_0 = -1...-1,
-// g_{m+1} = e_m): no per-lane branch, whatever the lanes' local vertices.
 #pragma once
 
 #include "fwd_fma.h"
 
 namespace fei {
 
-// Rows and slots a wave owns at most (the host cuts chunks to fit).
-constexpr int kAsmSlots = 256;
-constexpr int kAsmRows = 256;
+// Rows and slots a wave owns at most (the host cuts chunks to fit), and the
+// lanes per row.  Four lanes per row: 16 rows (240 slots of 3 x 3 blocks, the
+// 15 of a Kuhn vertex each) keep four 4-wave workgroups per CU, and a row's 24
+// incidences take 6 steps.
+constexpr int kAsmLanes = 4;
+constexpr int kAsmRows = 64 / kAsmLanes;
+constexpr int kAsmSlots = 240;
 
 template <int FORM, int DIM>
 struct AsmShape {
@@ -80,13 +82,24 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
     for (int k = lane; k < nslot * BS2; k += 64) acc[k] = 0.f;
     wave_sync();
 
+    // this lane's row and its share (every kAsmLanes-th incidence) of the row's list
+    const int part = lane / kAsmRows, local = lane % kAsmRows;
+    const bool has_row = local < nrows;
+    const int32_t row = r0 + (has_row ? local : 0);
+    const int32_t jb = has_row ? p.ptr[row] + part : 0;
+    const int32_t je = has_row ? p.ptr[row + 1] : 0;
+    const int b0 = has_row ? rp[local] : 0, b1 = has_row ? rp[local + 1] : 0;
+    // the wave steps through the longest share of its rows (je - jb >= 1 - kAsmLanes)
+    int steps = has_row ? (je - jb + kAsmLanes - 1) / kAsmLanes : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) steps = max(steps, __shfl_xor(steps, off));
+
     const float *__restrict__ mu = p.mu;
     const float *__restrict__ lam = p.lam;
-    const int32_t j0 = p.ptr[r0], j1 = p.ptr[r1];
-    for (int32_t jb = j0; jb < j1; jb += 64) {
-        const int32_t j = jb + lane;
-        const bool live = j < j1;
-        const int32_t ent = p.inc[live ? j : j0];
+    for (int it = 0; it < steps; ++it) {
+        const int32_t j = jb + kAsmLanes * it;
+        const bool live = has_row && j < je;
+        const int32_t ent = p.inc[live ? j : 0];
         const int64_t e = ent / NV;
         const int a = ent - int(e) * NV;
         // plain loads: every element is read once per vertex, by neighbouring rows
@@ -106,15 +119,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
         // each element counted once: at its incidence with local vertex 0
         count_flags(p.counters, live && a == 0 && flag, live && a == 0 && singular);
 
-        // row of this incidence and the slots of the element's vertices in it
-        int local = 0;
-#pragma unroll
-        for (int m = 0; m < NV; ++m) local = (a == m) ? v[m] - r0 : local;
-        const bool in_rows = live && local >= 0 && local < nrows;
-        const int b0 = in_rows ? rp[local] : 0, b1 = in_rows ? rp[local + 1] : 0;
         int slot[NV];
 #pragma unroll
-        for (int b = 0; b < NV; ++b) slot[b] = find_slot(col, b0, b1, v[b]);
+        for (int b = 0; b < NV; ++b) slot[b] = live ? find_slot(col, b0, b1, v[b]) : -1;
 
         // w[nu][c][d] = sum_mu g_a,mu T^{(mu c),(nu d)} (runtime a, compile-time T index)
         float w[DIM][NC][NC];
@@ -133,28 +140,33 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
                         r = (a == m + 1) ? Gf[sym_index(T::GD, m * NC + c, nu * NC + d)] : r;
                     w[nu][c][d] = r;
                 }
-        // blocks (a, b) = sum_nu g_b,nu w[nu], added into the row's slots
+        // blocks (a, b) = sum_nu g_b,nu w[nu], added into the row's slots by
+        // one part of the wave after the other (a part's rows are distinct)
 #pragma unroll
-        for (int b = 0; b < NV; ++b) {
-            const bool put = in_rows && slot[b] >= 0;
-            float *dst = acc + (put ? slot[b] : 0) * BS2;
+        for (int h = 0; h < kAsmLanes; ++h) {
+            if (part == h) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
+                for (int b = 0; b < NV; ++b) {
+                    if (slot[b] < 0) continue;
+                    float *dst = acc + slot[b] * BS2;
 #pragma unroll
-                for (int d = 0; d < NC; ++d) {
-                    float blk;
-                    if (b == 0) {
-                        float s = 0.f;
+                    for (int c = 0; c < NC; ++c)
 #pragma unroll
-                        for (int nu = 0; nu < DIM; ++nu) s += w[nu][c][d];
-                        blk = -s;
-                    } else {
-                        blk = w[b - 1][c][d];
-                    }
-                    if (put)
-                        __hip_atomic_fetch_add(dst + c * NC + d, blk, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+                        for (int d = 0; d < NC; ++d) {
+                            float blk;
+                            if (b == 0) {
+                                float s = 0.f;
+#pragma unroll
+                                for (int nu = 0; nu < DIM; ++nu) s += w[nu][c][d];
+                                blk = -s;
+                            } else {
+                                blk = w[b - 1][c][d];
+                            }
+                            dst[c * NC + d] += blk;
+                        }
                 }
+            }
+            wave_sync();
         }
     }
     wave_sync();
