@@ -167,6 +167,23 @@ def cube_mesh(nx: int, ny: int, nz: int, jitter: float = 0.15,
     return Mesh(coords, conn)
 
 
+def fan_mesh(nfan: int, seed: int) -> Mesh:
+    """A 2D fan: vertex 0 shared by nfan triangles around it (degree nfan, nfan
+    neighbours), beside a small jittered square mesh of ordinary degrees; the
+    elements in a random order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ang = np.sort(rng.uniform(0, 2 * np.pi, nfan))
+    ring = np.stack([np.cos(ang), np.sin(ang)], axis=1) * rng.uniform(0.8, 1.2, (nfan, 1))
+    sq = square_mesh(9, 0.2, seed + 1, np.float32)
+    coords = np.concatenate([[[0.0, 0.0]], ring, sq.coords + 3.0]).astype(np.float32)
+    k = np.arange(nfan)
+    fan = np.stack([np.zeros(nfan, np.int64), 1 + k, 1 + (k + 1) % nfan], 1)
+    conn = np.concatenate([fan, sq.conn + 1 + nfan]).astype(np.int32)
+    conn = np.ascontiguousarray(conn[rng.permutation(len(conn))])
+    _assert_positive(coords, conn)
+    return Mesh(coords, conn)
+
+
 def flatten_elements(mesh: Mesh, count: int, seed: int, ratio: float = 1e-3) -> Mesh:
     """Make ``count`` tets (chosen without replacement) near-degenerate.
 

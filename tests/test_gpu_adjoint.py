@@ -508,25 +508,11 @@ def test_deterministic_adjoint_matches_oracle_and_repeats(case):
                              gl).max() <= TOL_COEFF
 
 
-def _fan(nfan, seed):
-    """A 2D fan: vertex 0 shared by nfan triangles around it (degree nfan),
-    next to a small jittered square mesh (ordinary degrees)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    ang = np.sort(rng.uniform(0, 2 * np.pi, nfan))
-    ring = np.stack([np.cos(ang), np.sin(ang)], axis=1) * rng.uniform(0.8, 1.2, (nfan, 1))
-    sq = meshgen.square_mesh(9, 0.2, seed + 1, np.float32)
-    coords = np.concatenate([[[0.0, 0.0]], ring, sq.coords + 3.0]).astype(np.float32)
-    fan = np.stack([np.zeros(nfan, np.int64), 1 + np.arange(nfan), 1 + (np.arange(nfan) + 1) % nfan], 1)
-    conn = np.concatenate([fan, sq.conn + 1 + nfan]).astype(np.int32)
-    perm = rng.permutation(len(conn))          # incidences arrive in no particular order
-    return meshgen.Mesh(coords, np.ascontiguousarray(conn[perm]))
-
-
 @pytest.mark.parametrize("nfan", [63, 64, 65, 200])
 def test_deterministic_adjoint_high_degree_vertex(nfan):
     """Incidence lists up to 64 entries are ranked by a wave, longer ones
     heap-sorted: a vertex of degree 63 to 200 against the oracle, repeated."""
-    m = _fan(nfan, 97 + nfan)
+    m = meshgen.fan_mesh(nfan, 97 + nfan)
     dA = meshgen.upstream(m.n_elements, 3, 98)
     coords, conn = mesh_to_device(m)
     runs = [fei.integrate_adjoint(coords, conn, "laplace_p1", vec_to_device(dA),

@@ -121,6 +121,31 @@ def test_assembly_counts_fp64_elements_once():
     assert cnt.cpu().tolist() == [mesh.n_elements, 0]
 
 
+@pytest.mark.parametrize("nfan", [60, 200])
+def test_assembly_high_degree_vertex(nfan):
+    """A row of nfan + 1 blocks whose nfan incidences the four row owners share
+    unevenly, against the oracle, repeated bit for bit; a vertex with more
+    neighbours than a wave's accumulator holds is refused at plan creation."""
+    m = meshgen.fan_mesh(nfan, 111 + nfan)
+    asm, rowptr, colidx, vals = _gpu_assemble(m, "laplace_p1", None, None)
+    assert rowptr[1] - rowptr[0] == nfan + 1
+    K = _to_csr(asm, rowptr, colidx, vals)
+    Ko = oracle.assemble("laplace_p1", m.coords, m.conn)
+    assert np.array_equal(K.indptr, Ko.indptr) and np.array_equal(K.indices, Ko.indices)
+    S = _scale("laplace_p1", m.coords, m.conn, None, None, Ko.shape[0])
+    assert (np.abs(K.data - Ko.data) / S.data).max() <= TOL_ASM
+    _, _, _, vals2 = _gpu_assemble(m, "laplace_p1", None, None)
+    assert np.array_equal(vals.view(np.uint32), vals2.view(np.uint32))
+
+
+def test_assembly_refuses_a_row_beyond_the_accumulator():
+    m = meshgen.fan_mesh(300, 112)
+    coords, conn = mesh_to_device(m)
+    with pytest.raises(fei.FeiError) as ex:
+        fei.Assembly(coords, conn, "laplace_p1")
+    assert ex.value.status == fei._lib.FEI_EUNSUPPORTED
+
+
 def test_assembly_unused_vertices_and_rejections():
     """A vertex no element uses has an empty row; P2 forms and bad connectivity
     are refused at plan creation."""
