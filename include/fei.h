@@ -378,9 +378,10 @@ int fei_batch_run(fei_batch *b, void *stream);
 int fei_batch_run_adjoint(fei_batch *b, void *stream);
 /* Times the candidate configurations of the forward (adjoint = 0) or adjoint
  * (adjoint = 1, both gather settings: builds the vertex incidence first) graph
- * on `stream` -- running them, so outputs are written, and for the adjoint
- * dx/dy/dz receive one accumulation per trial -- then rebuilds that graph with
- * the fastest.  *chosen (if not NULL) receives it.                           */
+ * on `stream`, each as an instantiated graph launched as fei_batch_run does
+ * (one warm-up, the median of three) -- running them, so outputs are written,
+ * and for the adjoint dx/dy/dz receive one accumulation per trial -- then
+ * rebuilds that graph with the fastest.  *chosen (if not NULL) receives it.  */
 int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *chosen);
 int fei_batch_get_config(const fei_batch *b, int adjoint, fei_batch_config *out);
 /* Rebuilds the forward/adjoint graph with a given configuration (for example

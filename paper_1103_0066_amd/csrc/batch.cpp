@@ -544,14 +544,17 @@ int fei_batch_tune(fei_batch *b, int adjoint, void *stream, fei_batch_config *ch
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    // every candidate is timed as what run() launches: its instantiated graph
     int best = -1;
     float best_ms = 0.f;
     for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
-        if (enqueue(b, adjoint, cand[k], s) != hipSuccess) continue;  // warm-up
+        sd.cfg = cand[k];
+        if (build_graph(b, adjoint) != FEI_OK || !sd.exec) continue;
+        if (hipGraphLaunch(sd.exec, s) != hipSuccess) continue;  // warm-up
         float times[3];
         for (int r = 0; r < 3 && e == hipSuccess; ++r) {
             e = hipEventRecord(t0, s);
-            if (e == hipSuccess) e = enqueue(b, adjoint, cand[k], s);
+            if (e == hipSuccess) e = hipGraphLaunch(sd.exec, s);
             if (e == hipSuccess) e = hipEventRecord(t1, s);
             if (e == hipSuccess) e = hipEventSynchronize(t1);
             if (e == hipSuccess) e = hipEventElapsedTime(&times[r], t0, t1);
