@@ -231,7 +231,7 @@ struct FwdFmaTile {
         unique_entries<FORM, DIM>(Gf, Au);
     }
 
-    __device__ static void store(const FwdParams &p, int64_t e0, const float (&Au)[U::NU],
+    __device__ __forceinline__ static void store(const FwdParams &p, int64_t e0, const float (&Au)[U::NU],
                                  unsigned char *smem)
     {
         const int64_t E = p.m.n_elements;

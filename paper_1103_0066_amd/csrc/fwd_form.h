@@ -15,11 +15,16 @@
 // them with uniform addresses known at compile time, so they arrive through
 // the scalar cache as SGPR operands; C_e, J^-1 and |J| are per element.
 //
-// One lane per element.  Rows of A are produced RC at a time (RC*n floats in
+// One lane per element.  Symmetric forms whose order n is that of a built-in
+// form (3, 4, 6, 10, 12) form the n(n+1)/2 distinct entries and leave through
+// the FP32 forward's whole-matrix staging (each staged chunk one contiguous
+// run of matrices); the others produce rows RC at a time (RC*n floats in
 // registers), staged in LDS for the wave's 64 elements and stored with
 // consecutive lanes on consecutive 16-byte pieces.  Elements flagged by the
 // quality test build G in FP64.
 #pragma once
+
+#include <utility>
 
 #include "fwd_fma.h"
 
@@ -142,13 +147,59 @@ __device__ __forceinline__ float form_g(const FormG<DIM, DEG, NC, SYM, NOVAL> &G
     else return G[I * M + J];
 }
 
+// The FP32 forward tile whose whole-matrix store serves symmetric matrices of
+// order N (its store depends on N alone).
+template <int N>
+struct FormStore {
+    static constexpr bool OK = false;
+    static constexpr int LDS_BYTES = 0;
+};
+template <int F, int D>
+struct FormStoreOf {
+    static constexpr bool OK = true;
+    using Tile = FwdFmaTile<F, D, float, Traits<F, D>::N>;
+    static constexpr int LDS_BYTES = Tile::LDS_BYTES;
+};
+template <> struct FormStore<3> : FormStoreOf<LAP1, 2> {};
+template <> struct FormStore<4> : FormStoreOf<LAP1, 3> {};
+template <> struct FormStore<6> : FormStoreOf<ELA1, 2> {};
+template <> struct FormStore<10> : FormStoreOf<LAP2, 3> {};
+template <> struct FormStore<12> : FormStoreOf<ELA1, 3> {};
+
+constexpr int sym_first(int n, int u)
+{
+    int a = 0, b = 0;
+    sym_pair(n, u, a, b);
+    return a;
+}
+constexpr int sym_second(int n, int u)
+{
+    int a = 0, b = 0;
+    sym_pair(n, u, a, b);
+    return b;
+}
+
+// Au[u] = entry(I, J) for every distinct entry u = (I <= J) of an order-N
+// symmetric matrix, one instantiation per entry (an index sequence), so every
+// index is a constant and Au stays in registers.
+template <int N, typename F, int... Us>
+__device__ __forceinline__ void fill_sym(float (&Au)[N * (N + 1) / 2], const F &entry,
+                                         std::integer_sequence<int, Us...>)
+{
+    ((Au[Us] = entry(std::integral_constant<int, sym_first(N, Us)>::value,
+                     std::integral_constant<int, sym_second(N, Us)>::value)), ...);
+}
+
 template <int DIM, int DEG, int NC, bool SYM, bool NOVAL>
 __global__ __launch_bounds__(256) void form_kernel(FormParams p)
 {
     using SH = FormShape<DIM, DEG, NC, NOVAL>;
     constexpr int N = SH::N, NN = SH::NN, NB = SH::NB, ND = SH::ND, RC = SH::RC;
     constexpr int KD = DIM + 1;                     // operators per side of Khat
-    __shared__ __attribute__((aligned(16))) unsigned char smem[SH::LDS_BYTES];
+    constexpr bool WHOLE = SYM && FormStore<N>::OK;
+    constexpr int LDS = (WHOLE && FormStore<N>::LDS_BYTES > SH::LDS_BYTES) ? FormStore<N>::LDS_BYTES
+                                                                            : SH::LDS_BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS];
 
     const int lane = threadIdx.x & 63, wave = wave_id();
     const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * 256 + wave * 64;
@@ -214,7 +265,15 @@ __global__ __launch_bounds__(256) void form_kernel(FormParams p)
         return acc;
     };
 
-    if constexpr (RC == 0) {
+    if constexpr (WHOLE) {
+        // the distinct entries (I <= J), stored as the forward stores its matrices
+        float Au[N * (N + 1) / 2];
+        fill_sym<N>(Au, entry, std::make_integer_sequence<int, N * (N + 1) / 2>{});
+        FwdParams fp{};
+        fp.m = p.m;
+        fp.A = p.A;
+        FormStore<N>::Tile::store(fp, e0, Au, smem);
+    } else if constexpr (RC == 0) {
         if (live) {
             float *Ae = p.A + e * (int64_t)NN;
 #pragma unroll
