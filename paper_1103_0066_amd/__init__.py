@@ -348,8 +348,8 @@ class _IntegrateFn(torch.autograd.Function):
     vertex gradients come from fei_integrate_adjoint_det, in a fixed order."""
 
     @staticmethod
-    def forward(ctx, coords, mu, lam, conn, form, precision, tau):
-        ctx.form, ctx.tau = form, tau
+    def forward(ctx, coords, mu, lam, conn, form, precision, tau, adjoint_precision):
+        ctx.form, ctx.tau, ctx.adj_prec = form, tau, adjoint_precision
         ctx.save_for_backward(coords, mu, lam, conn)
         return integrate(coords, conn, form, mu, lam, precision=precision, tau=tau)
 
@@ -360,22 +360,26 @@ class _IntegrateFn(torch.autograd.Function):
         need_c = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
         det = torch.are_deterministic_algorithms_enabled() and coords.dtype == torch.float32
         dc, dmu, dlam = integrate_adjoint(coords, conn, ctx.form, dA, mu, lam, tau=ctx.tau,
-                                          coeff_grads=need_c, deterministic=det)
+                                          coeff_grads=need_c, deterministic=det,
+                                          precision=ctx.adj_prec)
         gc = dc.to(coords.dtype) if ctx.needs_input_grad[0] else None
         return (gc, dmu if ctx.needs_input_grad[1] else None,
-                dlam if ctx.needs_input_grad[2] else None, None, None, None, None)
+                dlam if ctx.needs_input_grad[2] else None, None, None, None, None, None)
 
 
 def element_matrices(coords: torch.Tensor, conn: torch.Tensor, form: str,
                      mu: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
-                     precision: str = "fp32", tau: float = 100.0) -> torch.Tensor:
+                     precision: str = "fp32", tau: float = 100.0,
+                     adjoint_precision: str = "fp32") -> torch.Tensor:
     """Autograd-aware element matrices: gradients flow to coords, mu and lam.
 
-    The backward is the FP32 adjoint of the exact operator for every
-    ``precision`` (for "fp16x2", "bf16x2", "bf16x3" the gradient of the exact A,
-    not of the split-precision A returned), accumulated in FP32 and cast to the
-    dtype of ``coords``; deterministic under torch.use_deterministic_algorithms."""
-    return _IntegrateFn.apply(coords, mu, lam, conn, form, precision, tau)
+    The backward is the adjoint of the exact operator for every ``precision``
+    (for "fp16x2", "bf16x2", "bf16x3" the gradient of the exact A, not of the
+    split-precision A returned), accumulated in FP32 and cast to the dtype of
+    ``coords``; deterministic under torch.use_deterministic_algorithms.
+    ``adjoint_precision`` other than "fp32" runs the backward's fold of dA on
+    the matrix cores (dA split into 16-bit terms; FP32 coordinates)."""
+    return _IntegrateFn.apply(coords, mu, lam, conn, form, precision, tau, adjoint_precision)
 
 
 from .batch import Batch  # noqa: E402

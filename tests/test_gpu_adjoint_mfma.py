@@ -207,3 +207,22 @@ def test_full_mfma_adjoint_sampled(prec):
     verr = float((np.abs(gg - go).max(axis=1)[ok] / sc[ok]).max())
     print(f"  sampled vertex err {verr:.3e}, coeff err {cerr:.3e}", flush=True)
     assert verr <= TOL[prec] and cerr <= TOL[prec]
+
+
+def test_autograd_backward_on_the_matrix_cores():
+    """element_matrices(..., adjoint_precision=...) runs the split-precision
+    adjoint as its backward: the same gradients as the direct call."""
+    m, form, mu, lam = _case("elast3d")
+    coords, conn = mesh_to_device(m)
+    c = coords.clone().requires_grad_(True)
+    mu_d = vec_to_device(mu).requires_grad_(True)
+    lam_d = vec_to_device(lam).requires_grad_(True)
+    dA = vec_to_device(meshgen.upstream(m.n_elements, 12, 211))
+    A = fei.element_matrices(c, conn, form, mu_d, lam_d, adjoint_precision="fp16x2")
+    (A * dA).sum().backward()
+    dc, dmu, dlam = fei.integrate_adjoint(coords, conn, form, dA, vec_to_device(mu),
+                                          vec_to_device(lam), precision="fp16x2")
+    tol = 1e-6
+    torch.testing.assert_close(c.grad, dc, rtol=0, atol=tol * float(dc.abs().max()))
+    torch.testing.assert_close(mu_d.grad, dmu, rtol=0, atol=tol * float(dmu.abs().max()))
+    torch.testing.assert_close(lam_d.grad, dlam, rtol=0, atol=tol * float(dlam.abs().max()))
