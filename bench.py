@@ -85,11 +85,12 @@ def stored_mfma() -> dict:
     vals = _profile_values("mfma_elastic_p1_3d_fwd.txt")
     out = {}
     for prec in ("fp16x2", "bf16x2", "bf16x3"):
-        try:
-            out[prec] = {"flops": float(vals[f"{prec}_mfma_flops_per_launch"]),
-                         "busy": float(vals[f"{prec}_mfma_busy_fraction"])}
-        except (KeyError, ValueError):
-            pass
+        for key in (prec, f"adjoint_{prec}"):
+            try:
+                out[key] = {"flops": float(vals[f"{key}_mfma_flops_per_launch"]),
+                            "busy": float(vals[f"{key}_mfma_busy_fraction"])}
+            except (KeyError, ValueError):
+                pass
     return out
 
 
@@ -638,6 +639,13 @@ def main():
             if "adjoint_fp32" in legs:
                 legs[name]["speedup_vs_fp32"] = (legs["adjoint_fp32"]["ms_per_launch"]
                                                  / legs[name]["ms_per_launch"])
+            if name in mfma:
+                fl = mfma[name]["flops"]
+                legs[name]["mfma"] = {
+                    "flops_per_launch": fl,
+                    "achieved_tflops": fl / (r["ms_per_launch"] * 1e-3) / 1e12,
+                    "peak_tflops": MFMA_PEAK_TFLOPS, "busy_fraction": mfma[name]["busy"],
+                    "source": "profiles/mfma_elastic_p1_3d_fwd.txt"}
             adj_acc(name, adj(0, prec=prec))
         if want(args, "adjoint_det_fp32", "adjoint"):
             r = time_leg([adj(k, True) for k in range(S)], args.steps, args.warmup,
