@@ -464,6 +464,9 @@ def form_leg(fei, meshgen, dev, args, legs, copy_gbs, acc, S):
     u, v = F.TrialFunction(el), F.TestFunction(el)
     mu, lam = F.Coefficient("mu"), F.Coefficient("lam")
     form = F.compile_form(2 * mu * F.inner(F.eps(u), F.eps(v)) + lam * F.div(u) * F.div(v))
+    generic = F.compile_form(2 * mu * F.inner(F.eps(u), F.eps(v)) + lam * F.div(u) * F.div(v))
+    progress(f"{name}: generating and compiling the form's kernel")
+    form.compile()
     w = meshgen.elast3d(args.n)
     m = w.mesh
     E = m.n_elements
@@ -476,8 +479,17 @@ def form_leg(fei, meshgen, dev, args, legs, copy_gbs, acc, S):
     nb = forward_bytes(E, m.n_vertices, 12, 3, True)
     legs[name] = rates(r, nb, E, paper_flops(3, 12), copy_gbs, stored_traffic(name))
     legs[name]["note"] = ("2 mu inner(eps(u), eps(v)) + lam div(u) div(v) through the form front "
-                          "end: Khat over values and reference derivatives and the G recipe at run "
-                          "time (the fp32 leg's kernel has them compiled in)")
+                          "end, with the kernel it generates and compiles for the form (W and Khat "
+                          "as constants; fei_form_compile)")
+    # the same form through the generic kernel (tables read at run time)
+    gfns = [(lambda k=k: generic.integrate(sets[k][0], sets[k][1],
+                                           {"mu": sets[k][2], "lam": sets[k][3]}, out=outs[k]))
+            for k in range(S)]
+    rg = time_leg(gfns, args.steps, args.warmup, name + "_generic")
+    legs[name + "_generic"] = rates(rg, nb, E, paper_flops(3, 12), copy_gbs,
+                                    stored_traffic(name + "_generic"))
+    legs[name + "_generic"]["note"] = "the same form through the generic kernel (W, Khat at run time)"
+    generic.close()
     if not args.no_accuracy:
         import oracle
         idx = np.sort(np.random.Generator(np.random.PCG64(14)).choice(E, 50000, replace=False))

@@ -479,6 +479,21 @@ int fei_form_reference_tensor(int dim, int degree, double *K, int64_t *len);
  * counters as for fei_integrate.  Asynchronous on `stream`.                 */
 int fei_form_integrate(const fei_weak_form *f, const fei_mesh *m, const float *coef, float *A,
                        const fei_options *opt, void *stream);
+/* Generates and compiles a kernel for this form (what a form compiler does,
+ * Sec. 3.2): the generic kernel's steps with W and Khat as compile-time
+ * constants, so their zero entries and the unused coefficients drop out;
+ * later fei_form_integrate calls launch it (same results up to the sign of
+ * zero: the dropped terms are exact zeros).  Runs the HIP compiler
+ * (FEI_HIPCC, else $ROCM_PATH/bin/hipcc, else /opt/rocm/bin/hipcc) on the
+ * current device's architecture with the kernel headers next to this library,
+ * and caches the code object in FEI_JIT_DIR (default $TMPDIR/fei_jit_<uid>)
+ * under a hash of the source, so a form already compiled is only loaded.
+ * Synchronous, seconds when compiling.  FEI_EUNSUPPORTED when the compiler or
+ * the headers are missing, FEI_EDEVICE when compiling or loading fails (the
+ * form keeps its generic kernel).                                          */
+int fei_form_compile(fei_weak_form *f);
+/* 1 when fei_form_compile has given the form its own kernel, else 0.         */
+int fei_form_is_compiled(const fei_weak_form *f);
 int fei_form_destroy(fei_weak_form *f);
 
 #ifdef __cplusplus

@@ -32,7 +32,8 @@ EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_d
            "fei_batch_copy_incidence", "fei_batch_destroy", "fei_assembly_create",
            "fei_assembly_info", "fei_assembly_copy_pattern", "fei_assemble",
            "fei_assembly_destroy", "fei_form_create", "fei_form_info", "fei_form_reference_tensor",
-           "fei_form_integrate", "fei_form_destroy", "fei_tune_forward", "fei_tune_lookup",
+           "fei_form_integrate", "fei_form_compile", "fei_form_is_compiled", "fei_form_destroy",
+           "fei_tune_forward", "fei_tune_lookup",
            "fei_tune_save", "fei_tune_load", "fei_tune_clear")
 
 
@@ -142,6 +143,8 @@ def load():
     lib.fei_form_reference_tensor.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(i64)]
     lib.fei_form_integrate.argtypes = [vp, ctypes.POINTER(FeiMesh), f32p, f32p,
                                        ctypes.POINTER(FeiOptions), vp]
+    lib.fei_form_compile.argtypes = [vp]
+    lib.fei_form_is_compiled.argtypes = [vp]
     lib.fei_form_destroy.argtypes = [vp]
     lib.fei_tune_forward.argtypes = [ctypes.POINTER(FeiMesh), ctypes.c_int, f32p, f32p, f32p,
                                      ctypes.POINTER(FeiOptions), vp, ctypes.POINTER(FeiTuneResult)]

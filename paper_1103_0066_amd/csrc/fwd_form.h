@@ -30,6 +30,22 @@
 
 namespace fei {
 
+// The form's tables (W, Khat) are the same for every element and never
+// written by the kernel: read through the constant address space, so the
+// uniform loads go through the scalar cache into SGPRs.
+typedef const __attribute__((address_space(4))) float form_tab_t;
+
+// Where a kernel reads the form's tables: the generic kernel reads them at
+// run time (FormTabRuntime); a kernel generated for one form (fei_form_compile)
+// has them as compile-time constants (CONST), so its zero entries drop out of
+// the G build and the contraction and its coefficient count is fixed.
+struct FormTabRuntime {
+    static constexpr bool CONST = false;
+    __device__ static float w(const FormParams &p, int i) { return ((form_tab_t *)p.W)[i]; }
+    __device__ static float k(const FormParams &p, int i) { return ((form_tab_t *)p.K)[i]; }
+    __device__ static int n_coef(const FormParams &p) { return p.n_coef; }
+};
+
 template <int DIM, int DEG, int NC, bool NOVAL = false>
 struct FormShape {
     // operators kept in G and Khat: value + DIM derivatives, or (NOVAL: the
@@ -68,14 +84,13 @@ using FormG = float[SYM ? FormShape<DIM, DEG, NC, NOVAL>::M * (FormShape<DIM, DE
 //   G_{(1+mu,c),(0,d)}      = s sum_alpha B_{mu alpha} C_{(1+alpha,c),(0,d)}
 //   G_{(1+mu,c),(1+nu,d)}   = s sum_{alpha,beta} B_{mu alpha} C_{(1+alpha,c),(1+beta,d)} B_{nu beta}
 // SYM: W is symmetric, so only the pairs I <= J of G are formed (sym_index).
-template <int DIM, int DEG, int NC, bool SYM, bool NOVAL, typename R>
+template <int DIM, int DEG, int NC, bool SYM, bool NOVAL, typename TAB, typename R>
 __device__ __forceinline__ void form_build_g(const FormParams &p, const R (&B)[DIM][DIM], R s,
                                              const float (&cf)[kFormMaxCoef + 1],
                                              FormG<DIM, DEG, NC, SYM, NOVAL> &G)
 {
     using SH = FormShape<DIM, DEG, NC, NOVAL>;
     constexpr int M = SH::M, MW = (DIM + 1) * NC, ND = DIM + 1;
-    const float *__restrict__ W = p.W;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -89,8 +104,10 @@ __device__ __forceinline__ void form_build_g(const FormParams &p, const R (&B)[D
                     R acc = R(0);
 #pragma unroll
                     for (int k = 0; k <= kFormMaxCoef; ++k)
-                        if (k <= p.n_coef)
-                            acc += R(cf[k]) * R(W[(k * MW + a * NC + c) * MW + b * NC + d]);
+                        if (k <= TAB::n_coef(p)) {
+                            const float wv = TAB::w(p, (k * MW + a * NC + c) * MW + b * NC + d);
+                            if (!TAB::CONST || wv != 0.f) acc += R(cf[k]) * R(wv);
+                        }
                     Cb[a][b] = acc;
                 }
             // Z[alpha][nu] = sum_beta C_{(1+alpha),(1+beta)} B_{nu beta}
@@ -190,8 +207,8 @@ __device__ __forceinline__ void fill_sym(float (&Au)[N * (N + 1) / 2], const F &
                      std::integral_constant<int, sym_second(N, Us)>::value)), ...);
 }
 
-template <int DIM, int DEG, int NC, bool SYM, bool NOVAL>
-__global__ __launch_bounds__(256) void form_kernel(FormParams p)
+template <int DIM, int DEG, int NC, bool SYM, bool NOVAL, typename TAB>
+__device__ __forceinline__ void form_body(const FormParams &p)
 {
     using SH = FormShape<DIM, DEG, NC, NOVAL>;
     constexpr int N = SH::N, NN = SH::NN, NB = SH::NB, ND = SH::ND, RC = SH::RC;
@@ -232,7 +249,7 @@ __global__ __launch_bounds__(256) void form_kernel(FormParams p)
             for (int mu = 0; mu < DIM; ++mu)
 #pragma unroll
                 for (int al = 0; al < DIM; ++al) B[mu][al] = adj[mu][al] * inv;
-            form_build_g<DIM, DEG, NC, SYM, NOVAL, float>(p, B, fabsf(det) * p.kscale, cf, G);
+            form_build_g<DIM, DEG, NC, SYM, NOVAL, TAB, float>(p, B, fabsf(det) * p.kscale, cf, G);
         } else {
             double Jd[DIM][DIM], adjd[DIM][DIM], Bd[DIM][DIM];
             jacobian<DIM>(xv, Jd);
@@ -243,7 +260,7 @@ __global__ __launch_bounds__(256) void form_kernel(FormParams p)
             for (int mu = 0; mu < DIM; ++mu)
 #pragma unroll
                 for (int al = 0; al < DIM; ++al) Bd[mu][al] = adjd[mu][al] * inv;
-            form_build_g<DIM, DEG, NC, SYM, NOVAL, double>(p, Bd, fabs(detd) * double(p.kscale), cf, G);
+            form_build_g<DIM, DEG, NC, SYM, NOVAL, TAB, double>(p, Bd, fabs(detd) * double(p.kscale), cf, G);
         }
     } else {
 #pragma unroll
@@ -251,7 +268,6 @@ __global__ __launch_bounds__(256) void form_kernel(FormParams p)
     }
     count_flags(p.counters, flag, singular);
 
-    const float *__restrict__ K = p.K;
     // entry (I, J) = ((i, c), (j, d)), I = NC i + c
     auto entry = [&](int I, int Jc) {
         const int i = I / NC, c = I % NC, j = Jc / NC, d = Jc % NC;
@@ -259,9 +275,11 @@ __global__ __launch_bounds__(256) void form_kernel(FormParams p)
 #pragma unroll
         for (int pp = 0; pp < ND; ++pp)
 #pragma unroll
-            for (int q = 0; q < ND; ++q)
-                acc = fmaf(form_g<DIM, DEG, NC, SYM, NOVAL>(G, pp * NC + c, q * NC + d),
-                           K[((i * NB + j) * KD + pp + SH::P0) * KD + q + SH::P0], acc);
+            for (int q = 0; q < ND; ++q) {
+                const float kv = TAB::k(p, ((i * NB + j) * KD + pp + SH::P0) * KD + q + SH::P0);
+                if (!TAB::CONST || kv != 0.f)
+                    acc = fmaf(form_g<DIM, DEG, NC, SYM, NOVAL>(G, pp * NC + c, q * NC + d), kv, acc);
+            }
         return acc;
     };
 
@@ -312,6 +330,12 @@ __global__ __launch_bounds__(256) void form_kernel(FormParams p)
             wave_sync();
         }
     }
+}
+
+template <int DIM, int DEG, int NC, bool SYM, bool NOVAL>
+__global__ __launch_bounds__(256) void form_kernel(FormParams p)
+{
+    form_body<DIM, DEG, NC, SYM, NOVAL, FormTabRuntime>(p);
 }
 
 }  // namespace fei

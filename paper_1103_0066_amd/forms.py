@@ -333,6 +333,16 @@ class Form:
             ctypes.byref(o), _stream(dev)))
         return out
 
+    def compile(self) -> "Form":
+        """Generates and compiles a kernel for this form (fei_form_compile: W and
+        Khat as constants; cached on disk), used by later integrate() calls."""
+        _lib.check(_lib.load().fei_form_compile(self._h))
+        return self
+
+    @property
+    def compiled(self) -> bool:
+        return bool(_lib.load().fei_form_is_compiled(self._h))
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.load().fei_form_destroy(self._h)

@@ -203,3 +203,9 @@ def test_form_create_rejects_before_any_device_work(args):
     n = ctypes.c_int64()
     assert lib.fei_form_reference_tensor(4, 1, None, ctypes.byref(n)) == _lib.FEI_EINVAL
     assert lib.fei_form_reference_tensor(3, 1, None, None) == _lib.FEI_EINVAL
+
+
+def test_form_compile_rejects_a_null_form():
+    lib = _lib.load()
+    assert lib.fei_form_compile(None) == _lib.FEI_EINVAL
+    assert lib.fei_form_is_compiled(None) == 0

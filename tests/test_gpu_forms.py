@@ -113,3 +113,55 @@ def test_form_rejects_bad_calls():
     ones = vec_to_device(np.ones(m2.n_elements, np.float32))
     with pytest.raises(ValueError):
         form.integrate(c2, k2, {"mu": ones, "lam": ones})
+
+
+# ---------------------------------------------------------------------------
+# forms with a kernel of their own (fei_form_compile)
+# ---------------------------------------------------------------------------
+
+COMPILED = [(3, 1, "elasticity"), (2, 2, "diffusion_reaction_advection"),
+            (3, 1, "vector_mass_coupled"), (3, 2, "laplace")]
+
+
+@pytest.mark.parametrize("dim,degree,name", COMPILED)
+def test_compiled_form_matches_generic_and_oracle(dim, degree, name, tmp_path, monkeypatch):
+    """The generated kernel (W and Khat as constants, zero terms dropped) gives
+    the generic kernel's results up to the sign of zero, and the oracle's at
+    the FP32 bound; ragged sizes included."""
+    monkeypatch.setenv("FEI_JIT_DIR", str(tmp_path))
+    a = dict(_forms(dim, degree))[name]
+    generic = F.compile_form(a)
+    compiled = F.compile_form(a).compile()
+    assert compiled.compiled and not generic.compiled
+    m = _mesh(dim, 350 + 10 * dim + degree, flat=4 if dim == 3 else 0)
+    rng = np.random.Generator(np.random.PCG64(19))
+    cf = {nm: np.exp(0.5 * rng.standard_normal(m.n_elements)).astype(np.float32)
+          for nm in generic.names}
+    print(f"[compiled form] {name} dim={dim} P{degree} E={m.n_elements}", flush=True)
+    W, names = F.lower(a)
+    Ao = oracle.integrate_general(degree, a.el.ncomp, W, m.coords, m.conn,
+                                  np.stack([cf[nm] for nm in names]) if names else ())
+    for E in sorted({min(x, m.n_elements) for x in (1, 63, 257, m.n_elements)}):
+        sub = meshgen.Mesh(m.coords, np.ascontiguousarray(m.conn[:E]))
+        coords, conn = mesh_to_device(sub)
+        c = {k: vec_to_device(v[:E]) for k, v in cf.items()}
+        out = torch.full((E, compiled.n, compiled.n), float("nan"), device="cuda")
+        Ac = compiled.integrate(coords, conn, c, out=out).cpu().numpy()
+        Ag = generic.integrate(coords, conn, c).cpu().numpy()
+        assert np.array_equal(np.abs(Ac), np.abs(Ag)), (E, float(np.abs(Ac - Ag).max()))
+        assert element_errors(Ac, Ao[:E]).max() <= TOL["fp32"]
+
+
+def test_compiled_form_is_cached(tmp_path, monkeypatch):
+    """A form compiled once is loaded from the cache by the next form object
+    with the same tables (one code object on disk)."""
+    import time
+    monkeypatch.setenv("FEI_JIT_DIR", str(tmp_path))
+    a = dict(_forms(2, 1))["laplace"]
+    F.compile_form(a).compile()
+    objs = sorted(p.name for p in tmp_path.iterdir())
+    assert len(objs) == 1 and objs[0].endswith(".co"), objs
+    t0 = time.perf_counter()
+    f2 = F.compile_form(a).compile()
+    assert f2.compiled and time.perf_counter() - t0 < 2.0
+    assert sorted(p.name for p in tmp_path.iterdir()) == objs
