@@ -10,9 +10,15 @@
 // fit the wave's LDS accumulator), and the kAsmLanes lanes r, r + kAsmRows, ..
 // own row r of it.  They walk the row's vertex-to-element incidences (e, a),
 // lane k of the row taking incidences k, k + kAsmLanes, .., recomputing
-// element e's geometric tensor (eq. 8 or its Lame
-// analogue, FP64 for flagged elements, exactly as the forward), forming row
-// block a of A_e and adding its n / NC blocks into the row's slots in LDS; the
+// element e's geometry (J, adj J, det J and the quality test, FP64 for flagged
+// elements, exactly as the forward), forming row block a of A_e = G_e : K and
+// adding its n / NC blocks into the row's slots in LDS.  The row block is
+// contracted in factored form: P1's K is rank one per vertex pair,
+// K^{ab}_{mu nu} = g_a,mu g_b,nu (reference gradients), and G_e is a sum of
+// products of adj J entries (eq. 8; the Lame analogue for elasticity), so
+// contracting g_a into adj J first (beta = g_a^T adj J) leaves 27 products for
+// the 3 x 3 x 3 row block of 3D elasticity instead of the 45 entries of G_e
+// and their contraction; the kernel is bound by its VALU issue.  The
 // slot of column vertex conn[e][b] is found by binary search in the row's
 // sorted column list.  The lanes of one part of the wave own distinct rows,
 // so their adds touch distinct slots: the parts add in turn with plain LDS
@@ -41,7 +47,7 @@ struct AsmShape {
     static constexpr int NC = T::NC;
     static constexpr int BS2 = NC * NC;                    // floats per block
     static constexpr int ACC = kAsmSlots * BS2;            // accumulator floats
-    static constexpr int WAVE_BYTES = 4 * (ACC + kAsmSlots + kAsmRows + 1 + 3);
+    static constexpr int WAVE_BYTES = 4 * (ACC + kAsmSlots);      // accumulator, columns
     static constexpr int LDS_BYTES = 4 * WAVE_BYTES;
 };
 
@@ -55,6 +61,77 @@ __device__ __forceinline__ int find_slot(const int *col, int b0, int b1, int v)
         else hi = mid;
     }
     return (lo < b1 && col[lo] == v) ? lo : -1;
+}
+
+// w[nu][c][d] = sum_mu g_a,mu G^{(mu c),(nu d)} of one element from adj J and
+// the weights of G (gf_weights): with beta = g_a^T adj J and m_nu = (adj J
+// beta)_nu, the Laplacian's row is wa m_nu and elasticity's is
+// wa (delta_cd m_nu + beta_d adj_nu,c) + wb beta_c adj_nu,d.  g_0 = (-1, .., -1),
+// g_a = e_{a-1} for a >= 1.
+template <int FORM, int DIM, typename R>
+__device__ __forceinline__ void row_of_g(const R (&adj)[DIM][DIM], R wa, R wb, int a,
+                                         float (&w)[DIM][Traits<FORM, DIM>::NC]
+                                                   [Traits<FORM, DIM>::NC])
+{
+    R beta[DIM];
+#pragma unroll
+    for (int al = 0; al < DIM; ++al) {
+        R s = adj[0][al];
+#pragma unroll
+        for (int m = 1; m < DIM; ++m) s += adj[m][al];
+        R r = -s;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) r = (a == m + 1) ? adj[m][al] : r;
+        beta[al] = r;
+    }
+#pragma unroll
+    for (int nu = 0; nu < DIM; ++nu) {
+        R mnu = adj[nu][0] * beta[0];
+#pragma unroll
+        for (int al = 1; al < DIM; ++al) mnu += adj[nu][al] * beta[al];
+        if constexpr (FORM != ELA1) {
+            w[nu][0][0] = float(wa * mnu);
+        } else {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    R t = wa * (beta[d] * adj[nu][c]) + wb * (beta[c] * adj[nu][d]);
+                    if (c == d) t += wa * mnu;
+                    w[nu][c][d] = float(t);
+                }
+        }
+    }
+}
+
+// The geometry of one element (FP32, or FP64 when the quality test flags it,
+// as the forward) and its row a of G_e : K (row_of_g).  Returns the flag;
+// *singular reports det J == 0 on the path taken.
+template <int FORM, int DIM>
+__device__ __forceinline__ bool row_block(const float (&xv)[DIM + 1][DIM], float mu, float lam,
+                                          float tau2, int a,
+                                          float (&w)[DIM][Traits<FORM, DIM>::NC]
+                                                    [Traits<FORM, DIM>::NC],
+                                          bool &singular)
+{
+    float J[DIM][DIM], adj[DIM][DIM];
+    jacobian<DIM>(xv, J);
+    const float det = adjugate(J, adj);
+    const bool flag = needs_fp64<DIM>(J, adj, det, tau2);
+    if (!flag) {
+        singular = false;
+        float wa, wb;
+        gf_weights<FORM, DIM>(det, mu, lam, wa, wb);
+        row_of_g<FORM, DIM>(adj, wa, wb, a, w);
+    } else {
+        double Jd[DIM][DIM], adjd[DIM][DIM], wa, wb;
+        jacobian<DIM>(xv, Jd);
+        const double detd = adjugate(Jd, adjd);
+        singular = detd == 0.0;
+        gf_weights<FORM, DIM>(detd, mu, lam, wa, wb);
+        row_of_g<FORM, DIM>(adjd, wa, wb, a, w);
+    }
+    return flag;
 }
 
 template <int FORM, int DIM>
@@ -71,24 +148,37 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
     if (chunk >= p.n_chunks) return;               // wave-uniform; no workgroup barrier below
     float *acc = reinterpret_cast<float *>(smem + wave * SH::WAVE_BYTES);
     int *col = reinterpret_cast<int *>(acc + SH::ACC);
-    int *rp = col + kAsmSlots;
 
     const int32_t r0 = p.chunks[chunk], r1 = p.chunks[chunk + 1];
     const int nrows = r1 - r0;
     const int32_t s0 = p.rowptr[r0], s1 = p.rowptr[r1];
     const int nslot = s1 - s0;
-    for (int k = lane; k <= nrows; k += 64) rp[k] = p.rowptr[r0 + k] - s0;
-    for (int k = lane; k < nslot; k += 64) col[k] = p.colidx[s0 + k];
-    for (int k = lane; k < nslot * BS2; k += 64) acc[k] = 0.f;
-    wave_sync();
 
-    // this lane's row and its share (every kAsmLanes-th incidence) of the row's list
+    // this lane's row and its share (every kAsmLanes-th incidence) of the row's
+    // list; the per-row pointers are loaded together with the chunk's columns
     const int part = lane / kAsmRows, local = lane % kAsmRows;
     const bool has_row = local < nrows;
-    const int32_t row = r0 + (has_row ? local : 0);
-    const int32_t jb = has_row ? p.ptr[row] + part : 0;
-    const int32_t je = has_row ? p.ptr[row + 1] : 0;
-    const int b0 = has_row ? rp[local] : 0, b1 = has_row ? rp[local + 1] : 0;
+    const int32_t row = r0 + (has_row ? local : 0);                  // in range
+    const int32_t i0 = p.ptr[row], i1 = p.ptr[row + 1];
+    const int32_t c0 = p.rowptr[row], c1 = p.rowptr[row + 1];
+    const int32_t jb = has_row ? i0 + part : 0, je = has_row ? i1 : 0;
+    const int b0 = has_row ? c0 - s0 : 0, b1 = has_row ? c1 - s0 : 0;
+    if (nslot > 0) {
+        // all of the chunk's column loads in flight at once (indexes clamped into the chunk)
+        constexpr int CL = (kAsmSlots + 63) / 64;
+        int c[CL];
+#pragma unroll
+        for (int i = 0; i < CL; ++i) c[i] = p.colidx[s0 + min(lane + 64 * i, nslot - 1)];
+#pragma unroll
+        for (int i = 0; i < CL; ++i)
+            if (lane + 64 * i < nslot) col[lane + 64 * i] = c[i];
+    }
+    // 16-byte zeroing: the accumulator is a whole number of 16-byte pieces
+    static_assert(SH::ACC % 4 == 0 && SH::WAVE_BYTES % 16 == 0, "16-byte accumulator pieces");
+    for (int k = 4 * lane; k < nslot * BS2; k += 256)
+        *reinterpret_cast<float4 *>(acc + k) = make_float4(0.f, 0.f, 0.f, 0.f);
+    wave_sync();
+
     // the wave steps through the longest share of its rows (je - jb >= 1 - kAsmLanes)
     int steps = has_row ? (je - jb + kAsmLanes - 1) / kAsmLanes : 0;
 #pragma unroll
@@ -96,77 +186,93 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
 
     const float *__restrict__ mu = p.mu;
     const float *__restrict__ lam = p.lam;
-    for (int it = 0; it < steps; ++it) {
-        const int32_t j = jb + kAsmLanes * it;
-        const bool live = has_row && j < je;
-        const int32_t ent = p.inc[live ? j : 0];
-        const int64_t e = ent / NV;
-        const int a = ent - int(e) * NV;
-        // plain loads: every element is read once per vertex, by neighbouring rows
+    // the incidence list is empty when no row has a step: nothing may be read then
+    if (steps > 0) {
+        // Software pipeline over the steps: each step issues the coordinate
+        // loads of its own element, the connectivity of the next step's element
+        // and the incidence two steps ahead before its arithmetic, so of the
+        // three dependent loads only the last is exposed.  Lanes past the end
+        // of their row's list read entry 0 (in bounds: the list is not empty)
+        // and add nothing.
+        auto inc_at = [&](int it) -> int32_t {
+            const int32_t j = jb + kAsmLanes * it;
+            return p.inc[(has_row && j < je) ? j : 0];
+        };
+        int32_t ent = inc_at(0);
         int v[NV];
 #pragma unroll
-        for (int m = 0; m < NV; ++m) v[m] = p.m.conn[e * NV + m];
-        float xv[NV][DIM];
-        gather<DIM>(p.m, v, xv);
-        float me = 0.f, le = 0.f;
-        if constexpr (FORM == ELA1) {
-            me = mu[e];
-            le = lam[e];
-        }
-        float Gf[T::G];
-        bool singular = false;
-        const bool flag = geometry<FORM, DIM>(xv, me, le, p.tau2, Gf, singular);
-        // each element counted once: at its incidence with local vertex 0
-        count_flags(p.counters, live && a == 0 && flag, live && a == 0 && singular);
-
-        int slot[NV];
+        for (int m = 0; m < NV; ++m) v[m] = p.m.conn[int64_t(ent / NV) * NV + m];
+        int32_t ent1 = inc_at(1);
+        for (int it = 0; it < steps; ++it) {
+            const bool live = has_row && jb + kAsmLanes * it < je;
+            const int64_t e = ent / NV;
+            const int a = ent - int(e) * NV;
+            // plain loads: every element is read once per vertex, by neighbouring rows
+            float xv[NV][DIM];
+            gather<DIM>(p.m, v, xv);
+            float me = 0.f, le = 0.f;
+            if constexpr (FORM == ELA1) {
+                me = mu[e];
+                le = lam[e];
+            }
+            int v1[NV];
 #pragma unroll
-        for (int b = 0; b < NV; ++b) slot[b] = live ? find_slot(col, b0, b1, v[b]) : -1;
+            for (int m = 0; m < NV; ++m) v1[m] = p.m.conn[int64_t(ent1 / NV) * NV + m];
+            const int32_t ent2 = inc_at(it + 2);
 
-        // w[nu][c][d] = sum_mu g_a,mu T^{(mu c),(nu d)} (runtime a, compile-time T index)
-        float w[DIM][NC][NC];
+            // w[nu][c][d] = sum_mu g_a,mu G^{(mu c),(nu d)}: row a of G_e : K before its
+            // contraction with g_b
+            float w[DIM][NC][NC];
+            bool singular = false;
+            const bool flag = row_block<FORM, DIM>(xv, me, le, p.tau2, a, w, singular);
+            // each element counted once: at its incidence with local vertex 0
+            count_flags(p.counters, live && a == 0 && flag, live && a == 0 && singular);
+
+            int slot[NV];
 #pragma unroll
-        for (int nu = 0; nu < DIM; ++nu)
+            for (int b = 0; b < NV; ++b) slot[b] = live ? find_slot(col, b0, b1, v[b]) : -1;
+            // blocks (a, b) = sum_nu g_b,nu w[nu]: w[b - 1] for b >= 1, minus their sum for b = 0
+            float w0[NC][NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
                 for (int d = 0; d < NC; ++d) {
-                    float s = 0.f;
+                    float t = w[0][c][d];
 #pragma unroll
-                    for (int m = 0; m < DIM; ++m) s += Gf[sym_index(T::GD, m * NC + c, nu * NC + d)];
-                    float r = -s;
-#pragma unroll
-                    for (int m = 0; m < DIM; ++m)
-                        r = (a == m + 1) ? Gf[sym_index(T::GD, m * NC + c, nu * NC + d)] : r;
-                    w[nu][c][d] = r;
+                    for (int nu = 1; nu < DIM; ++nu) t += w[nu][c][d];
+                    w0[c][d] = -t;
                 }
-        // blocks (a, b) = sum_nu g_b,nu w[nu], added into the row's slots by
-        // one part of the wave after the other (a part's rows are distinct)
+            // added into the row's slots by one part of the wave after the
+            // other: the lanes of a part own distinct rows, so no two of them
+            // touch the same float.  A lane's NV slots are distinct (the
+            // element's vertices are), so its reads are issued before its
+            // writes, and the next part's reads, issued after them, see them
+            // (a wave's LDS operations complete in order).
 #pragma unroll
-        for (int h = 0; h < kAsmLanes; ++h) {
-            if (part == h) {
+            for (int h = 0; h < kAsmLanes; ++h) {
+                if (part == h) {
+                    float old[NV][BS2];
 #pragma unroll
-                for (int b = 0; b < NV; ++b) {
-                    if (slot[b] < 0) continue;
-                    float *dst = acc + slot[b] * BS2;
+                    for (int b = 0; b < NV; ++b)
 #pragma unroll
-                    for (int c = 0; c < NC; ++c)
+                        for (int i = 0; i < BS2; ++i) old[b][i] = acc[max(slot[b], 0) * BS2 + i];
 #pragma unroll
-                        for (int d = 0; d < NC; ++d) {
-                            float blk;
-                            if (b == 0) {
-                                float s = 0.f;
+                    for (int b = 0; b < NV; ++b) {
+                        if (slot[b] < 0) continue;
 #pragma unroll
-                                for (int nu = 0; nu < DIM; ++nu) s += w[nu][c][d];
-                                blk = -s;
-                            } else {
-                                blk = w[b - 1][c][d];
-                            }
-                            dst[c * NC + d] += blk;
-                        }
+                        for (int c = 0; c < NC; ++c)
+#pragma unroll
+                            for (int d = 0; d < NC; ++d)
+                                acc[slot[b] * BS2 + c * NC + d] =
+                                    old[b][c * NC + d] + (b == 0 ? w0[c][d] : w[b - 1][c][d]);
+                    }
                 }
+                wave_sync();      // keeps the parts apart and in order
             }
-            wave_sync();
+            ent = ent1;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) v[m] = v1[m];
+            ent1 = ent2;
         }
     }
     wave_sync();

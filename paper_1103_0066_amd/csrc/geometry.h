@@ -108,16 +108,15 @@ __device__ __forceinline__ bool needs_fp64(const float (&J)[DIM][DIM],
     return !(nj * na <= tau2 * (det * det)) || det == 0.f;
 }
 
-// Folded geometric tensor: Gf[sym_index(p, q)], p <= q, scaled by
-// Traits::SCALE = vol_ref / KDEN so that A = sum_g Gf[g] Kf[g] with the
-// integer reference tensor.
+// Folded geometric tensor from adj J and the element's weights: wa = vol_ref
+// / (KDEN |det J|) for the Laplacian forms; wa = that weight times mu and wb =
+// times lam for elasticity.  Gf[sym_index(p, q)], p <= q, so that A = sum_g
+// Gf[g] Kf[g] with the integer reference tensor.
 template <int FORM, int DIM, typename R>
-__device__ __forceinline__ void build_gf(const R (&adj)[DIM][DIM], R det, float mu, float lam,
-                                         float (&Gf)[Traits<FORM, DIM>::G])
+__device__ __forceinline__ void build_gf_weighted(const R (&adj)[DIM][DIM], R wa, R wb,
+                                                  float (&Gf)[Traits<FORM, DIM>::G])
 {
     using T = Traits<FORM, DIM>;
-    const R s = det < R(0) ? -det : det;
-    const R w = R(T::SCALE) / s;
     R M[DIM][DIM];
 #pragma unroll
     for (int m = 0; m < DIM; ++m)
@@ -132,19 +131,39 @@ __device__ __forceinline__ void build_gf(const R (&adj)[DIM][DIM], R det, float 
 #pragma unroll
         for (int m = 0; m < DIM; ++m)
 #pragma unroll
-            for (int n = m; n < DIM; ++n) Gf[sym_index(DIM, m, n)] = float(w * M[m][n]);
+            for (int n = m; n < DIM; ++n) Gf[sym_index(DIM, m, n)] = float(wa * M[m][n]);
     } else {
-        const R mw = w * R(mu), lw = w * R(lam);
 #pragma unroll
         for (int p = 0; p < T::GD; ++p)
 #pragma unroll
             for (int q = p; q < T::GD; ++q) {
                 const int m = p / DIM, c = p % DIM, n = q / DIM, d = q % DIM;
-                R t = mw * (adj[m][d] * adj[n][c]) + lw * (adj[m][c] * adj[n][d]);
-                if (c == d) t += mw * M[m][n];
+                R t = wa * (adj[m][d] * adj[n][c]) + wb * (adj[m][c] * adj[n][d]);
+                if (c == d) t += wa * M[m][n];
                 Gf[sym_index(T::GD, p, q)] = float(t);
             }
     }
+}
+
+// The element's weights of build_gf_weighted.
+template <int FORM, int DIM, typename R>
+__device__ __forceinline__ void gf_weights(R det, float mu, float lam, R &wa, R &wb)
+{
+    const R s = det < R(0) ? -det : det;
+    const R w = R(Traits<FORM, DIM>::SCALE) / s;
+    wa = FORM == ELA1 ? w * R(mu) : w;
+    wb = FORM == ELA1 ? w * R(lam) : R(0);
+}
+
+// Folded geometric tensor of the element (Sec. 3, eq. 8; the Lame analogue for
+// elasticity), scaled by Traits::SCALE = vol_ref / KDEN.
+template <int FORM, int DIM, typename R>
+__device__ __forceinline__ void build_gf(const R (&adj)[DIM][DIM], R det, float mu, float lam,
+                                         float (&Gf)[Traits<FORM, DIM>::G])
+{
+    R wa, wb;
+    gf_weights<FORM, DIM>(det, mu, lam, wa, wb);
+    build_gf_weighted<FORM, DIM>(adj, wa, wb, Gf);
 }
 
 // Whole geometry stage for one element (gather already done).  FP64
