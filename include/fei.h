@@ -414,7 +414,9 @@ int fei_batch_destroy(fei_batch *b);
  * with i, in increasing order, even where the sum is zero.
  *
  * A plan holds the pattern and the vertex-to-element incidence the kernel
- * walks; it is built once per connectivity and serves any coordinates and
+ * walks, each row's incidences ordered in steps of four whose elements share
+ * no vertex but the row's (so a step's blocks are added without conflicts);
+ * it is built once per connectivity and serves any coordinates and
  * coefficients on that connectivity. */
 typedef struct fei_assembly fei_assembly;
 

@@ -8,24 +8,24 @@
 // Rows are gathered, not scattered, and every row has owners: a wave takes a
 // contiguous range of up to kAsmRows rows (a host-built chunk whose blocks
 // fit the wave's LDS accumulator), and the kAsmLanes lanes r, r + kAsmRows, ..
-// own row r of it.  They walk the row's vertex-to-element incidences (e, a),
-// lane k of the row taking incidences k, k + kAsmLanes, .., recomputing
-// element e's geometry (J, adj J, det J and the quality test, FP64 for flagged
-// elements, exactly as the forward), forming row block a of A_e = G_e : K and
-// adding its n / NC blocks into the row's slots in LDS.  The row block is
-// contracted in factored form: P1's K is rank one per vertex pair,
-// K^{ab}_{mu nu} = g_a,mu g_b,nu (reference gradients), and G_e is a sum of
-// products of adj J entries (eq. 8; the Lame analogue for elasticity), so
-// contracting g_a into adj J first (beta = g_a^T adj J) leaves 27 products for
-// the 3 x 3 x 3 row block of 3D elasticity instead of the 45 entries of G_e
-// and their contraction; the kernel is bound by its VALU issue.  The
-// slot of column vertex conn[e][b] is found by binary search in the row's
-// sorted column list.  The lanes of one part of the wave own distinct rows,
-// so their adds touch distinct slots: the parts add in turn with plain LDS
-// read-modify-writes, no atomics (LDS float atomics, where the lanes of a row
-// collide on its slots, measured 6x slower), and every sum runs in the order
-// of the row's incidence list, so every run gives the same bits.  The
-// finished rows leave as one contiguous run of values.
+// own row r of it.  They walk the row's vertex-to-element incidences (e, a) in
+// the plan's schedule, lane k of the row taking entries k, k + kAsmLanes, ..,
+// recomputing element e's geometry (J, adj J, det J and the quality test, FP64
+// for flagged elements, exactly as the forward) and forming row block a of
+// A_e = G_e : K.  The row block is contracted in factored form: P1's K is rank
+// one per vertex pair, K^{ab}_{mu nu} = g_a,mu g_b,nu (reference gradients), and
+// G_e is a sum of products of adj J entries (eq. 8; the Lame analogue for
+// elasticity), so contracting g_a into adj J first (beta = g_a^T adj J) leaves
+// 27 products for the 3 x 3 x 3 row block of 3D elasticity instead of the 45
+// entries of G_e and their contraction.  The schedule puts a row's incidences
+// in steps of kAsmLanes whose elements share no vertex but the row's, so the
+// off-diagonal blocks of one step land on distinct slots and the whole wave
+// adds them into LDS at once with plain read-modify-writes (no atomics); the
+// diagonal block, which every incidence of the row touches, is summed in the
+// lanes' registers and added by the row's lanes in turn at the end.  The slot
+// of column vertex conn[e][b] is found by binary search in the row's sorted
+// column list.  Every sum runs in an order fixed by the plan, so every run
+// gives the same bits.  The finished rows leave as one contiguous run of values.
 //
 #pragma once
 
@@ -67,11 +67,12 @@ __device__ __forceinline__ int find_slot(const int *col, int b0, int b1, int v)
 // the weights of G (gf_weights): with beta = g_a^T adj J and m_nu = (adj J
 // beta)_nu, the Laplacian's row is wa m_nu and elasticity's is
 // wa (delta_cd m_nu + beta_d adj_nu,c) + wb beta_c adj_nu,d.  g_0 = (-1, .., -1),
-// g_a = e_{a-1} for a >= 1.
+// g_a = e_{a-1} for a >= 1.  dg is the block (a, a) of A_e.
 template <int FORM, int DIM, typename R>
 __device__ __forceinline__ void row_of_g(const R (&adj)[DIM][DIM], R wa, R wb, int a,
                                          float (&w)[DIM][Traits<FORM, DIM>::NC]
-                                                   [Traits<FORM, DIM>::NC])
+                                                   [Traits<FORM, DIM>::NC],
+                                         float (&dg)[Traits<FORM, DIM>::NC][Traits<FORM, DIM>::NC])
 {
     R beta[DIM];
 #pragma unroll
@@ -102,6 +103,23 @@ __device__ __forceinline__ void row_of_g(const R (&adj)[DIM][DIM], R wa, R wb, i
                 }
         }
     }
+    // the diagonal block (a, a): g_a contracted on both sides, beta . beta and
+    // beta beta^T
+    R bb = beta[0] * beta[0];
+#pragma unroll
+    for (int al = 1; al < DIM; ++al) bb += beta[al] * beta[al];
+    if constexpr (FORM != ELA1) {
+        dg[0][0] = float(wa * bb);
+    } else {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                R t = wa * (beta[d] * beta[c]) + wb * (beta[c] * beta[d]);
+                if (c == d) t += wa * bb;
+                dg[c][d] = float(t);
+            }
+    }
 }
 
 // The geometry of one element (FP32, or FP64 when the quality test flags it,
@@ -112,6 +130,8 @@ __device__ __forceinline__ bool row_block(const float (&xv)[DIM + 1][DIM], float
                                           float tau2, int a,
                                           float (&w)[DIM][Traits<FORM, DIM>::NC]
                                                     [Traits<FORM, DIM>::NC],
+                                          float (&dg)[Traits<FORM, DIM>::NC]
+                                                     [Traits<FORM, DIM>::NC],
                                           bool &singular)
 {
     float J[DIM][DIM], adj[DIM][DIM];
@@ -122,14 +142,14 @@ __device__ __forceinline__ bool row_block(const float (&xv)[DIM + 1][DIM], float
         singular = false;
         float wa, wb;
         gf_weights<FORM, DIM>(det, mu, lam, wa, wb);
-        row_of_g<FORM, DIM>(adj, wa, wb, a, w);
+        row_of_g<FORM, DIM>(adj, wa, wb, a, w, dg);
     } else {
         double Jd[DIM][DIM], adjd[DIM][DIM], wa, wb;
         jacobian<DIM>(xv, Jd);
         const double detd = adjugate(Jd, adjd);
         singular = detd == 0.0;
         gf_weights<FORM, DIM>(detd, mu, lam, wa, wb);
-        row_of_g<FORM, DIM>(adjd, wa, wb, a, w);
+        row_of_g<FORM, DIM>(adjd, wa, wb, a, w, dg);
     }
     return flag;
 }
@@ -186,14 +206,20 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
 
     const float *__restrict__ mu = p.mu;
     const float *__restrict__ lam = p.lam;
-    // the incidence list is empty when no row has a step: nothing may be read then
+    // each lane's share of its row's diagonal block, added into LDS at the end
+    float dsum[NC][NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int d = 0; d < NC; ++d) dsum[c][d] = 0.f;
+    // the schedule is empty when no row has a step: nothing may be read then
     if (steps > 0) {
         // Software pipeline over the steps: each step issues the coordinate
         // loads of its own element, the connectivity of the next step's element
-        // and the incidence two steps ahead before its arithmetic, so of the
-        // three dependent loads only the last is exposed.  Lanes past the end
-        // of their row's list read entry 0 (in bounds: the list is not empty)
-        // and add nothing.
+        // and the schedule entry two steps ahead before its arithmetic, so of
+        // the three dependent loads only the last is exposed.  Lanes past the
+        // end of their row's schedule read entry 0, padding entries (-1) read
+        // element 0; neither adds anything.
         auto inc_at = [&](int it) -> int32_t {
             const int32_t j = jb + kAsmLanes * it;
             return p.inc[(has_row && j < je) ? j : 0];
@@ -201,12 +227,12 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
         int32_t ent = inc_at(0);
         int v[NV];
 #pragma unroll
-        for (int m = 0; m < NV; ++m) v[m] = p.m.conn[int64_t(ent / NV) * NV + m];
+        for (int m = 0; m < NV; ++m) v[m] = p.m.conn[int64_t(max(ent, 0) / NV) * NV + m];
         int32_t ent1 = inc_at(1);
         for (int it = 0; it < steps; ++it) {
-            const bool live = has_row && jb + kAsmLanes * it < je;
-            const int64_t e = ent / NV;
-            const int a = ent - int(e) * NV;
+            const bool live = has_row && jb + kAsmLanes * it < je && ent >= 0;
+            const int64_t e = max(ent, 0) / NV;
+            const int a = max(ent, 0) - int(e) * NV;
             // plain loads: every element is read once per vertex, by neighbouring rows
             float xv[NV][DIM];
             gather<DIM>(p.m, v, xv);
@@ -217,21 +243,27 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
             }
             int v1[NV];
 #pragma unroll
-            for (int m = 0; m < NV; ++m) v1[m] = p.m.conn[int64_t(ent1 / NV) * NV + m];
+            for (int m = 0; m < NV; ++m) v1[m] = p.m.conn[int64_t(max(ent1, 0) / NV) * NV + m];
             const int32_t ent2 = inc_at(it + 2);
 
             // w[nu][c][d] = sum_mu g_a,mu G^{(mu c),(nu d)}: row a of G_e : K before its
-            // contraction with g_b
-            float w[DIM][NC][NC];
+            // contraction with g_b; dg = block (a, a)
+            float w[DIM][NC][NC], dg[NC][NC];
             bool singular = false;
-            const bool flag = row_block<FORM, DIM>(xv, me, le, p.tau2, a, w, singular);
+            const bool flag = row_block<FORM, DIM>(xv, me, le, p.tau2, a, w, dg, singular);
             // each element counted once: at its incidence with local vertex 0
             count_flags(p.counters, live && a == 0 && flag, live && a == 0 && singular);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int d = 0; d < NC; ++d) dsum[c][d] += live ? dg[c][d] : 0.f;
 
+            // off-diagonal blocks (a, b), b != a: sum_nu g_b,nu w[nu] = w[b - 1]
+            // for b >= 1, minus their sum for b = 0
             int slot[NV];
 #pragma unroll
-            for (int b = 0; b < NV; ++b) slot[b] = live ? find_slot(col, b0, b1, v[b]) : -1;
-            // blocks (a, b) = sum_nu g_b,nu w[nu]: w[b - 1] for b >= 1, minus their sum for b = 0
+            for (int b = 0; b < NV; ++b)
+                slot[b] = (live && b != a) ? find_slot(col, b0, b1, v[b]) : -1;
             float w0[NC][NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -242,37 +274,44 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
                     for (int nu = 1; nu < DIM; ++nu) t += w[nu][c][d];
                     w0[c][d] = -t;
                 }
-            // added into the row's slots by one part of the wave after the
-            // other: the lanes of a part own distinct rows, so no two of them
-            // touch the same float.  A lane's NV slots are distinct (the
-            // element's vertices are), so its reads are issued before its
-            // writes, and the next part's reads, issued after them, see them
-            // (a wave's LDS operations complete in order).
+            // The step's elements share no vertex but the row's (the plan's
+            // schedule), and rows are distinct, so no two lanes touch one block:
+            // the whole wave adds at once with plain read-modify-writes, a
+            // lane's reads (its slots are distinct) before its writes.
+            float old[NV][BS2];
 #pragma unroll
-            for (int h = 0; h < kAsmLanes; ++h) {
-                if (part == h) {
-                    float old[NV][BS2];
+            for (int b = 0; b < NV; ++b)
 #pragma unroll
-                    for (int b = 0; b < NV; ++b)
+                for (int i = 0; i < BS2; ++i) old[b][i] = acc[max(slot[b], 0) * BS2 + i];
 #pragma unroll
-                        for (int i = 0; i < BS2; ++i) old[b][i] = acc[max(slot[b], 0) * BS2 + i];
+            for (int b = 0; b < NV; ++b) {
+                if (slot[b] < 0) continue;
 #pragma unroll
-                    for (int b = 0; b < NV; ++b) {
-                        if (slot[b] < 0) continue;
+                for (int c = 0; c < NC; ++c)
 #pragma unroll
-                        for (int c = 0; c < NC; ++c)
-#pragma unroll
-                            for (int d = 0; d < NC; ++d)
-                                acc[slot[b] * BS2 + c * NC + d] =
-                                    old[b][c * NC + d] + (b == 0 ? w0[c][d] : w[b - 1][c][d]);
-                    }
-                }
-                wave_sync();      // keeps the parts apart and in order
+                    for (int d = 0; d < NC; ++d)
+                        acc[slot[b] * BS2 + c * NC + d] =
+                            old[b][c * NC + d] + (b == 0 ? w0[c][d] : w[b - 1][c][d]);
             }
+            wave_sync();
             ent = ent1;
 #pragma unroll
             for (int m = 0; m < NV; ++m) v[m] = v1[m];
             ent1 = ent2;
+        }
+    }
+    // the diagonal blocks: the kAsmLanes lanes of a row add their shares in turn
+    {
+        const int sd = has_row ? find_slot(col, b0, b1, row) : -1;
+#pragma unroll
+        for (int h = 0; h < kAsmLanes; ++h) {
+            if (part == h && sd >= 0) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int d = 0; d < NC; ++d) acc[sd * BS2 + c * NC + d] += dsum[c][d];
+            }
+            wave_sync();
         }
     }
     wave_sync();

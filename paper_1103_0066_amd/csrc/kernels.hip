@@ -553,6 +553,7 @@ hipError_t launch_vertex_gather_one(const GatherItem &it, hipStream_t s)
 
 int assemble_chunk_rows() { return kAsmRows; }
 int assemble_chunk_slots() { return kAsmSlots; }
+int assemble_lanes() { return kAsmLanes; }
 
 hipError_t launch_assemble(int form, int dim, const AsmParams &p, hipStream_t s)
 {

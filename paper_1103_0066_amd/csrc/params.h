@@ -169,7 +169,7 @@ hipError_t launch_form(int dim, int degree, int ncomp, bool sym, bool noval, con
 struct AsmParams {
     MeshView m;
     const float *mu, *lam;           // elasticity only
-    const int32_t *ptr, *inc;        // vertex-to-element incidence (CSR, sorted)
+    const int32_t *ptr, *inc;        // per row: its incidences in steps of kAsmLanes (-1 pads)
     const int32_t *rowptr, *colidx;  // the pattern: CSR over vertices, sorted columns
     const int32_t *chunks;           // [n_chunks + 1]: first row of each wave's chunk
     int64_t n_chunks;
@@ -180,6 +180,7 @@ struct AsmParams {
 // Rows (kAsmRows) and blocks (kAsmSlots) one chunk may hold.
 int assemble_chunk_rows();
 int assemble_chunk_slots();
+int assemble_lanes();
 hipError_t launch_assemble(int form, int dim, const AsmParams &p, hipStream_t s);
 
 }  // namespace fei
