@@ -433,6 +433,15 @@ int fei_assembly_info(const fei_assembly *a, int64_t *n_rows, int64_t *nnz, int3
  * (int32), asynchronously on `stream`.                                      */
 int fei_assembly_copy_pattern(const fei_assembly *a, int32_t *rowptr, int32_t *colidx,
                               void *stream);
+/* The incidence schedule the kernel walks: *n_entries receives its length;
+ * with ptr and inc non-NULL, copies ptr [n_rows + 1] and inc [n_entries]
+ * (device int32, asynchronously on `stream`).  Row v's entries are
+ * inc[ptr[v] .. ptr[v + 1]), in steps of 4 (ptr[v + 1] - ptr[v] is a
+ * multiple of 4); an entry is e * (dim + 1) + a (element e, local vertex a of
+ * v) or -1 (padding).  The elements of one step share no vertex but v, and
+ * every incidence of v appears once.                                        */
+int fei_assembly_copy_schedule(const fei_assembly *a, int64_t *n_entries, int32_t *ptr,
+                               int32_t *inc, void *stream);
 /* values [nnz][NC][NC] FP32 (device, overwritten) = K of mesh m, which must
  * have the dimension, vertex and element counts of the plan's mesh and the
  * same connectivity (not re-checked: the kernel trusts the plan); FP32

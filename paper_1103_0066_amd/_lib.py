@@ -30,7 +30,7 @@ EXPORTS = ("fei_abi_version", "fei_status_str", "fei_last_error", "fei_options_d
            "fei_reference_tensor_coefficient", "fei_validate_mesh", "fei_batch_create", "fei_batch_run",
            "fei_batch_run_adjoint", "fei_batch_tune", "fei_batch_get_config", "fei_batch_set_config",
            "fei_batch_copy_incidence", "fei_batch_destroy", "fei_assembly_create",
-           "fei_assembly_info", "fei_assembly_copy_pattern", "fei_assemble",
+           "fei_assembly_info", "fei_assembly_copy_pattern", "fei_assembly_copy_schedule", "fei_assemble",
            "fei_assembly_destroy", "fei_form_create", "fei_form_info", "fei_form_reference_tensor",
            "fei_form_integrate", "fei_form_compile", "fei_form_is_compiled", "fei_form_destroy",
            "fei_tune_forward", "fei_tune_lookup",
@@ -134,6 +134,7 @@ def load():
     lib.fei_assembly_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(i32)]
     lib.fei_assembly_copy_pattern.argtypes = [vp, vp, vp, vp]
+    lib.fei_assembly_copy_schedule.argtypes = [vp, ctypes.POINTER(i64), vp, vp, vp]
     lib.fei_assemble.argtypes = [vp, ctypes.POINTER(FeiMesh), f32p, f32p, f32p,
                                  ctypes.POINTER(FeiOptions), vp]
     lib.fei_assembly_destroy.argtypes = [vp]

@@ -42,6 +42,21 @@ class Assembly:
             torch.cuda.current_stream(dev).cuda_stream))
         return rowptr, colidx[:self.nnz]
 
+    def schedule(self):
+        """(ptr [n_rows + 1], inc [n_entries]) int32 device tensors: each row's
+        incidences e * (dim + 1) + a in steps of four whose elements share no
+        vertex but the row's, -1 padding a step."""
+        dev = self.coords.device
+        lib = _lib.load()
+        n = ctypes.c_int64()
+        _lib.check(lib.fei_assembly_copy_schedule(self._h, ctypes.byref(n), None, None, None))
+        ptr = torch.empty(self.n_rows + 1, dtype=torch.int32, device=dev)
+        inc = torch.empty(max(n.value, 1), dtype=torch.int32, device=dev)
+        _lib.check(lib.fei_assembly_copy_schedule(self._h, ctypes.byref(n), ptr.data_ptr(),
+                                                  inc.data_ptr(),
+                                                  torch.cuda.current_stream(dev).cuda_stream))
+        return ptr, inc[:n.value]
+
     def assemble(self, mu: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None, *,
                  coords: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
                  tau: float = 100.0, counters: Optional[torch.Tensor] = None) -> torch.Tensor:

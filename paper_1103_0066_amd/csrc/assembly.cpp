@@ -20,7 +20,7 @@ using namespace fei::host;
 struct fei_assembly {
     int form = 0, dim = 0, nc = 1;
     int64_t n_vertices = 0, n_elements = 0, nnz = 0;
-    int64_t n_chunks = 0;
+    int64_t n_chunks = 0, n_sched = 0;
     int32_t *d_ptr = nullptr, *d_inc = nullptr, *d_rowptr = nullptr, *d_colidx = nullptr,
             *d_chunks = nullptr;
 };
@@ -219,6 +219,7 @@ int fei_assembly_create(const fei_mesh *m, int form, fei_assembly **out)
     a->n_elements = E;
     a->nnz = int64_t(colidx.size());
     a->n_chunks = int64_t(chunks.size()) - 1;
+    a->n_sched = int64_t(sinc.size());
     if ((rc = upload(sptr, &a->d_ptr)) || (rc = upload(sinc, &a->d_inc)) ||
         (rc = upload(rowptr, &a->d_rowptr)) || (rc = upload(colidx, &a->d_colidx)) ||
         (rc = upload(chunks, &a->d_chunks))) {
@@ -248,6 +249,21 @@ int fei_assembly_copy_pattern(const fei_assembly *a, int32_t *rowptr, int32_t *c
     if (e == hipSuccess && a->nnz > 0)
         e = hipMemcpyAsync(colidx, a->d_colidx, size_t(a->nnz) * 4, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? FEI_OK : hip_fail(e, "pattern copy");
+}
+
+int fei_assembly_copy_schedule(const fei_assembly *a, int64_t *n_entries, int32_t *ptr,
+                               int32_t *inc, void *stream)
+{
+    if (!a || !n_entries) return fail(FEI_EINVAL, "bad argument");
+    *n_entries = a->n_sched;
+    if (!ptr && !inc) return FEI_OK;
+    if (!ptr || (!inc && a->n_sched > 0)) return fail(FEI_EINVAL, "ptr or inc is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(ptr, a->d_ptr, size_t(a->n_vertices + 1) * 4,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && a->n_sched > 0)
+        e = hipMemcpyAsync(inc, a->d_inc, size_t(a->n_sched) * 4, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? FEI_OK : hip_fail(e, "schedule copy");
 }
 
 int fei_assemble(const fei_assembly *a, const fei_mesh *m, const float *mu, const float *lam,

@@ -138,6 +138,46 @@ def test_assembly_high_degree_vertex(nfan):
     assert np.array_equal(vals.view(np.uint32), vals2.view(np.uint32))
 
 
+@pytest.mark.parametrize("case", ["lap2d", "elast3d", "fan", "kuhn"])
+def test_assembly_schedule_is_conflict_free(case):
+    """The plan's schedule, which the kernel's unserialized adds rely on: each
+    row lists every incidence of its vertex exactly once, in steps of four
+    (-1 padding) whose elements share no vertex but the row's; on the Kuhn
+    cube the search reaches ceil(n / 4) steps for nearly every interior row."""
+    if case == "fan":
+        m, form = meshgen.fan_mesh(200, 113), "laplace_p1"
+    elif case == "kuhn":
+        m, form = meshgen.elast3d(12).mesh, "elastic_p1"
+    else:
+        m, form = _case(case)[:2]
+    coords, conn = mesh_to_device(m)
+    asm = fei.Assembly(coords, conn, form)
+    ptr, inc = (t.cpu().numpy() for t in asm.schedule())
+    nv = m.conn.shape[1]
+    want = [[] for _ in range(m.n_vertices)]
+    for e, row in enumerate(m.conn):
+        for a, v in enumerate(row):
+            want[v].append(e * nv + a)
+    assert ptr[0] == 0 and np.all(np.diff(ptr) % 4 == 0) and ptr[-1] == len(inc)
+    tight = rows24 = 0
+    for v in range(m.n_vertices):
+        ent = inc[ptr[v]:ptr[v + 1]]
+        assert sorted(ent[ent >= 0].tolist()) == sorted(want[v])
+        for st in ent.reshape(-1, 4):
+            seen = set()
+            for x in st[st >= 0]:
+                e, a = divmod(int(x), nv)
+                assert m.conn[e, a] == v
+                others = set(m.conn[e].tolist()) - {v}
+                assert not (others & seen)
+                seen |= others
+        if len(want[v]) == 24:
+            rows24 += 1
+            tight += len(ent) == 24
+    if case == "kuhn":
+        assert rows24 > 0 and tight >= 0.99 * rows24
+
+
 def test_assembly_refuses_a_row_beyond_the_accumulator():
     m = meshgen.fan_mesh(300, 112)
     coords, conn = mesh_to_device(m)
