@@ -277,7 +277,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
             // The step's elements share no vertex but the row's (the plan's
             // schedule), and rows are distinct, so no two lanes touch one block:
             // the whole wave adds at once with plain read-modify-writes, a
-            // lane's reads (its slots are distinct) before its writes.
+            // lane's reads before its writes (its slots are distinct: an
+            // element's vertices are; one that lists a vertex twice is singular,
+            // and the entries it reaches are not finite either way).
             float old[NV][BS2];
 #pragma unroll
             for (int b = 0; b < NV; ++b)
