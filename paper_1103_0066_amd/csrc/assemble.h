@@ -123,8 +123,8 @@ __device__ __forceinline__ void row_of_g(const R (&adj)[DIM][DIM], R wa, R wb, i
 }
 
 // The geometry of one element (FP32, or FP64 when the quality test flags it,
-// as the forward) and its row a of G_e : K (row_of_g).  Returns the flag;
-// *singular reports det J == 0 on the path taken.
+// as the forward) and its row a of G_e : K (row_of_g, in FP32).  Returns the
+// flag; *singular reports det J == 0 on the path taken.
 template <int FORM, int DIM>
 __device__ __forceinline__ bool row_block(const float (&xv)[DIM + 1][DIM], float mu, float lam,
                                           float tau2, int a,
@@ -138,19 +138,27 @@ __device__ __forceinline__ bool row_block(const float (&xv)[DIM + 1][DIM], float
     jacobian<DIM>(xv, J);
     const float det = adjugate(J, adj);
     const bool flag = needs_fp64<DIM>(J, adj, det, tau2);
+    float wa, wb;
+    singular = false;
     if (!flag) {
-        singular = false;
-        float wa, wb;
         gf_weights<FORM, DIM>(det, mu, lam, wa, wb);
-        row_of_g<FORM, DIM>(adj, wa, wb, a, w, dg);
     } else {
-        double Jd[DIM][DIM], adjd[DIM][DIM], wa, wb;
+        // J, adj J, det J and the weights in FP64 (where FP32 loses the
+        // element), rounded for the FP32 contraction, whose error is then
+        // normwise FP32 as for every other element
+        double Jd[DIM][DIM], adjd[DIM][DIM], wad, wbd;
         jacobian<DIM>(xv, Jd);
         const double detd = adjugate(Jd, adjd);
         singular = detd == 0.0;
-        gf_weights<FORM, DIM>(detd, mu, lam, wa, wb);
-        row_of_g<FORM, DIM>(adjd, wa, wb, a, w, dg);
+        gf_weights<FORM, DIM>(detd, mu, lam, wad, wbd);
+#pragma unroll
+        for (int m = 0; m < DIM; ++m)
+#pragma unroll
+            for (int n = 0; n < DIM; ++n) adj[m][n] = float(adjd[m][n]);
+        wa = float(wad);
+        wb = float(wbd);
     }
+    row_of_g<FORM, DIM>(adj, wa, wb, a, w, dg);
     return flag;
 }
 
