@@ -706,6 +706,22 @@ def main():
         SL = max(S, -(-2 * MALL_BYTES // forward_bytes(El, Nl, 4, 3, False)) + 1)
         lsets = replicate(torch, dev, (ml.soa(), ml.conn), SL)
         lb = forward_bytes(El, Nl, 4, 3, False)
+        # reference at this size: a plain device copy moving the same bytes (half
+        # read, half written), over as many buffer pairs as the leg rotates
+        lcopy_gbs = copy_gbs
+        if want(args, "copy_laplace3d_size", "ref") and (want(args, "laplace3d_fp32", "laplace")
+                                                         or want(args, "laplace3d_fp16x2", "laplace")):
+            half = lb // 8
+            csrc = [torch.ones(half, dtype=torch.float32, device=dev) for _ in range(SL)]
+            cdst = [torch.empty_like(x) for x in csrc]
+            rc = time_leg([(lambda k=k: cdst[k].copy_(csrc[k])) for k in range(SL)], args.steps,
+                          args.warmup, "copy_laplace3d_size")
+            lcopy_gbs = 2 * half * 4 / (rc["ms_per_launch"] * 1e-3) / 1e9
+            legs["copy_laplace3d_size_reference"] = dict(
+                rc, gbs=lcopy_gbs, frac=lcopy_gbs / HBM_PEAK_GBS, traffic_bytes_per_launch=2 * half * 4,
+                buffer_sets=SL, note="device copy moving the 3D P1 Laplacian forward's bytes; the "
+                "Laplacian forwards' frac_of_measured_copy is taken against it")
+            del csrc, cdst
         Al = [torch.empty((El, 4, 4), dtype=torch.float32, device=dev) for _ in range(SL)]
         for prec in ("fp32", "fp16x2"):
             name = f"laplace3d_{prec}"
@@ -714,7 +730,7 @@ def main():
             fns = [(lambda k=k: fei.integrate(lsets[k][0], lsets[k][1], "laplace_p1",
                                               precision=prec, out=Al[k])) for k in range(SL)]
             r = time_leg(fns, args.steps, args.warmup, name)
-            legs[name] = rates(r, lb, El, paper_flops(3, 4), copy_gbs,
+            legs[name] = rates(r, lb, El, paper_flops(3, 4), lcopy_gbs,
                                stored_traffic(f"laplace_p1_3d_fwd_{prec}"))
         if not args.no_accuracy and "laplace3d_fp32" in legs:
             import oracle
