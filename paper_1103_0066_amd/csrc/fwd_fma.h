@@ -165,10 +165,8 @@ struct FwdFmaTile {
     static constexpr int NCH = WHOLE ? 64 / EC : S::NCHUNK;
     static constexpr int LDS_BYTES =
         PACKED ? 4 * 64 * S::NN * 4 : ((R > 0) ? 4 * EC * S::STR * 4 : 0);
-    // Staged stores: non-temporal for the 576-byte elasticity matrices, plain
-    // for the smaller ones (measured on MI355X: 177 vs 182 us for 3D
-    // elasticity, 133 vs 125 us for the 3D P2 Laplacian).
-    static constexpr bool NT_STORES = (T::N >= 12);
+    // Staged stores: non-temporal or plain per matrix size (nt_matrix_stores)
+    static constexpr bool NT_STORES = nt_matrix_stores<T::N>();
     __device__ static void put(f32x4_t *dst, f32x4_t v)
     {
         if constexpr (NT_STORES) store_out(dst, v);

@@ -123,11 +123,10 @@ struct MfmaTile {
     using S = MfmaShape<FORM, DIM, PREC>;
     using L = MfmaLds<FORM, DIM, PREC>;
     static constexpr int FRAG_BYTES = L::AREG ? 0 : S::NFRAG * 16;
-    // non-temporal stores for the 576-byte elasticity matrices only, as in
-    // the FP32 form
+    // non-temporal or plain stores per matrix size, as in the FP32 form
     __device__ static void put(f32x4_t *dst, f32x4_t v)
     {
-        if constexpr (T::N >= 12) store_out(dst, v);
+        if constexpr (nt_matrix_stores<T::N>()) store_out(dst, v);
         else *dst = v;
     }
     static constexpr int LDS_BYTES = FRAG_BYTES + 4 * L::WBYTES + 256 * 4;

@@ -28,6 +28,17 @@ __device__ __forceinline__ void store_out(f32x4_t *dst, f32x4_t v)
     __builtin_nontemporal_store(v, dst);
 }
 
+// Whether the staged element-matrix stores of n x n matrices are non-temporal,
+// per size as measured on MI355X: yes for the 4 x 4 (3D P1 Laplacian: 32.3-33.0
+// vs 34.2-35.0 us) and 12 x 12 (3D elasticity: 177 vs 182 us) matrices, no for
+// the 10 x 10 ones (3D P2 Laplacian: 125 vs 133 us, the L2 combining their
+// shorter runs better).
+template <int N>
+constexpr bool nt_matrix_stores()
+{
+    return N >= 12 || N == 4;
+}
+
 template <int DIM>
 __device__ __forceinline__ void load_conn(const int32_t *__restrict__ conn, int64_t e,
                                           int (&v)[DIM + 1])
