@@ -29,14 +29,15 @@ __device__ __forceinline__ void store_out(f32x4_t *dst, f32x4_t v)
 }
 
 // Whether the staged element-matrix stores of n x n matrices are non-temporal,
-// per size as measured on MI355X: yes for the 4 x 4 (3D P1 Laplacian: 32.3-33.0
-// vs 34.2-35.0 us) and 12 x 12 (3D elasticity: 177 vs 182 us) matrices, no for
-// the 10 x 10 ones (3D P2 Laplacian: 125 vs 133 us, the L2 combining their
-// shorter runs better).
+// per size as measured on MI355X: yes for 3 x 3 (2D P1 Laplacian, 2.1 M
+// triangles: 23.1 vs 25.4 us), 4 x 4 (3D P1 Laplacian: 32.3-33.0 vs 34.2-35.0
+// us), 6 x 6 (2D elasticity: 65.1 vs 69.4 us) and 12 x 12 (3D elasticity: 177
+// vs 182 us), no for 10 x 10 (3D P2 Laplacian: 121-124 vs 128-130 us, the L2
+// combining their runs better).
 template <int N>
 constexpr bool nt_matrix_stores()
 {
-    return N >= 12 || N == 4;
+    return N != 10;
 }
 
 template <int DIM>
