@@ -415,9 +415,10 @@ int fei_batch_destroy(fei_batch *b);
  *
  * A plan holds the pattern and the vertex-to-element incidence the kernel
  * walks, each row's incidences ordered in steps of four whose elements share
- * no vertex but the row's (so a step's blocks are added without conflicts);
- * it is built once per connectivity and serves any coordinates and
- * coefficients on that connectivity. */
+ * no vertex but the row's (so a step's blocks are added without conflicts),
+ * with the slots of each incidence's element vertices in the row (4 bytes
+ * per entry); it is built once per connectivity and serves any coordinates
+ * and coefficients on that connectivity. */
 typedef struct fei_assembly fei_assembly;
 
 /* Builds the plan of mesh m (its connectivity; coordinates are not read).

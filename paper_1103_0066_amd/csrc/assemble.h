@@ -23,8 +23,8 @@
 // adds them into LDS at once with plain read-modify-writes (no atomics); the
 // diagonal block, which every incidence of the row touches, is summed in the
 // lanes' registers and added by the row's lanes in turn at the end.  The slot
-// of column vertex conn[e][b] is found by binary search in the row's sorted
-// column list.  Every sum runs in an order fixed by the plan, so every run
+// of column vertex conn[e][b] in the row's sorted column list comes with the
+// schedule entry (one byte per vertex, computed by the plan).  Every sum runs in an order fixed by the plan, so every run
 // gives the same bits.  The finished rows leave as one contiguous run of values.
 //
 #pragma once
@@ -40,6 +40,7 @@ namespace fei {
 constexpr int kAsmLanes = 4;
 constexpr int kAsmRows = 64 / kAsmLanes;
 constexpr int kAsmSlots = 240;
+static_assert(kAsmSlots <= 256, "a row's slots are addressed by one byte in the plan");
 
 template <int FORM, int DIM>
 struct AsmShape {
@@ -228,15 +229,21 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
         // the three dependent loads only the last is exposed.  Lanes past the
         // end of their row's schedule read entry 0, padding entries (-1) read
         // element 0; neither adds anything.
-        auto inc_at = [&](int it) -> int32_t {
+        auto entry_at = [&](int it, int32_t &ent, uint32_t &sl) {
             const int32_t j = jb + kAsmLanes * it;
-            return p.inc[(has_row && j < je) ? j : 0];
+            const int32_t jj = (has_row && j < je) ? j : 0;
+            ent = p.inc[jj];
+            sl = uint32_t(p.slots[jj]);
         };
-        int32_t ent = inc_at(0);
+        int32_t ent;
+        uint32_t sl;
+        entry_at(0, ent, sl);
         int v[NV];
 #pragma unroll
         for (int m = 0; m < NV; ++m) v[m] = p.m.conn[int64_t(max(ent, 0) / NV) * NV + m];
-        int32_t ent1 = inc_at(1);
+        int32_t ent1;
+        uint32_t sl1;
+        entry_at(1, ent1, sl1);
         for (int it = 0; it < steps; ++it) {
             const bool live = has_row && jb + kAsmLanes * it < je && ent >= 0;
             const int64_t e = max(ent, 0) / NV;
@@ -252,7 +259,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
             int v1[NV];
 #pragma unroll
             for (int m = 0; m < NV; ++m) v1[m] = p.m.conn[int64_t(max(ent1, 0) / NV) * NV + m];
-            const int32_t ent2 = inc_at(it + 2);
+            int32_t ent2;
+            uint32_t sl2;
+            entry_at(it + 2, ent2, sl2);
 
             // w[nu][c][d] = sum_mu g_a,mu G^{(mu c),(nu d)}: row a of G_e : K before its
             // contraction with g_b; dg = block (a, a)
@@ -270,8 +279,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
             // for b >= 1, minus their sum for b = 0
             int slot[NV];
 #pragma unroll
-            for (int b = 0; b < NV; ++b)
-                slot[b] = (live && b != a) ? find_slot(col, b0, b1, v[b]) : -1;
+            for (int b = 0; b < NV; ++b)    // the plan's slot bytes, relative to the row's first
+                slot[b] = (live && b != a) ? b0 + int((sl >> (8 * b)) & 255u) : -1;
             float w0[NC][NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -305,9 +314,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmParams p)
             }
             wave_sync();
             ent = ent1;
+            sl = sl1;
 #pragma unroll
             for (int m = 0; m < NV; ++m) v[m] = v1[m];
             ent1 = ent2;
+            sl1 = sl2;
         }
     }
     // the diagonal blocks: the kAsmLanes lanes of a row add their shares in turn

@@ -22,14 +22,14 @@ struct fei_assembly {
     int64_t n_vertices = 0, n_elements = 0, nnz = 0;
     int64_t n_chunks = 0, n_sched = 0;
     int32_t *d_ptr = nullptr, *d_inc = nullptr, *d_rowptr = nullptr, *d_colidx = nullptr,
-            *d_chunks = nullptr;
+            *d_chunks = nullptr, *d_slots = nullptr;
 };
 
 namespace {
 
 void release(fei_assembly *a)
 {
-    for (int32_t *p : {a->d_ptr, a->d_inc, a->d_rowptr, a->d_colidx, a->d_chunks})
+    for (int32_t *p : {a->d_ptr, a->d_inc, a->d_rowptr, a->d_colidx, a->d_chunks, a->d_slots})
         if (p) (void)hipFree(p);
     delete a;
 }
@@ -131,6 +131,24 @@ int fei_assembly_create(const fei_mesh *m, int form, fei_assembly **out)
             sptr[v + 1] = int32_t(sinc.size());
         }
     }
+    // per schedule entry, the slots of its element's vertices in the row's
+    // sorted columns, relative to the row's first (one byte per vertex: a row
+    // has at most max_slots < 256 columns)
+    std::vector<int32_t> sslot(sinc.size(), 0);
+    for (int64_t v = 0; v < Nv; ++v) {
+        const int32_t *c0 = colidx.data() + rowptr[v], *c1 = colidx.data() + rowptr[v + 1];
+        for (int32_t j = sptr[v]; j < sptr[v + 1]; ++j) {
+            if (sinc[j] < 0) continue;
+            const int64_t e = sinc[j] / nv;
+            uint32_t packed = 0;
+            for (int b = 0; b < nv; ++b) {
+                const int32_t w = conn[size_t(e) * nv + b];
+                const uint32_t rel = uint32_t(std::lower_bound(c0, c1, w) - c0);
+                packed |= rel << (8 * b);
+            }
+            sslot[j] = int32_t(packed);
+        }
+    }
 
     fei_assembly *a = new (std::nothrow) fei_assembly();
     if (!a) return fail(FEI_ENOMEM, "assembly plan");
@@ -142,7 +160,7 @@ int fei_assembly_create(const fei_mesh *m, int form, fei_assembly **out)
     a->nnz = int64_t(colidx.size());
     a->n_chunks = int64_t(chunks.size()) - 1;
     a->n_sched = int64_t(sinc.size());
-    if ((rc = upload(sptr, &a->d_ptr)) || (rc = upload(sinc, &a->d_inc)) ||
+    if ((rc = upload(sptr, &a->d_ptr)) || (rc = upload(sinc, &a->d_inc)) || (rc = upload(sslot, &a->d_slots)) ||
         (rc = upload(rowptr, &a->d_rowptr)) || (rc = upload(colidx, &a->d_colidx)) ||
         (rc = upload(chunks, &a->d_chunks))) {
         release(a);
@@ -212,6 +230,7 @@ int fei_assemble(const fei_assembly *a, const fei_mesh *m, const float *mu, cons
     p.lam = lam;
     p.ptr = a->d_ptr;
     p.inc = a->d_inc;
+    p.slots = a->d_slots;
     p.rowptr = a->d_rowptr;
     p.colidx = a->d_colidx;
     p.chunks = a->d_chunks;

@@ -170,6 +170,7 @@ struct AsmParams {
     MeshView m;
     const float *mu, *lam;           // elasticity only
     const int32_t *ptr, *inc;        // per row: its incidences in steps of kAsmLanes (-1 pads)
+    const int32_t *slots;            // per entry: its element's vertices' slots in the row, bytes
     const int32_t *rowptr, *colidx;  // the pattern: CSR over vertices, sorted columns
     const int32_t *chunks;           // [n_chunks + 1]: first row of each wave's chunk
     int64_t n_chunks;
